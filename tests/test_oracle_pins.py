@@ -1,0 +1,337 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics,
+not by the oracle itself.  CPU only.
+
+Each test names what a plausible mistake in the oracle would break.
+"""
+import numpy as np
+import pytest
+import scipy.optimize as so
+import scipy.sparse as sp
+
+import oracle as O
+from oracle.pcg import pcg
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import random_state, rel
+
+
+def general(seed, n=7, m=6, me=2, mg=4, a_sparse=False, h_kind="dense"):
+    return O.from_spec(W.random_bounded_qp(seed, n, m, me, mg, a_sparse=a_sparse,
+                                           h_kind=h_kind))
+
+
+# ---------------------------------------------------------------- residuals
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_residuals_vanish_at_barrier_stationary_point(seed):
+    """Build data so that (x, lam, s) is a stationary point of the barrier
+    problem of eq. (2): the constraint rows fix l, u, lx, ux, b from x and s;
+    lam * s = mu comes from d/ds of -mu log s; p from d/dx of the Lagrangian.
+    Every residual block of eq. (3) must then vanish.  A wrong sign in any
+    block breaks this."""
+    rng = np.random.default_rng(seed)
+    n, m, me, mu = 6, 5, 2, 0.3
+    spec = W.random_bounded_qp(seed, n, m, me, 3)
+    prob = O.from_spec(spec)
+    S = O.index_sets(prob)
+    x = rng.standard_normal(n)
+    s_lA, s_uA = rng.uniform(0.5, 2, S.L.size), rng.uniform(0.5, 2, S.U.size)
+    s_lx, s_ux = rng.uniform(0.5, 2, S.Lx.size), rng.uniform(0.5, 2, S.Ux.size)
+    lam_lA, lam_uA, lam_lx, lam_ux = mu / s_lA, mu / s_uA, mu / s_lx, mu / s_ux
+    lam_e = rng.standard_normal(me)
+    A = prob.A
+    prob.l = np.full(m, -np.inf); prob.u = np.full(m, np.inf)
+    prob.l[S.L] = A[S.L] @ x - s_lA           # A x - s_l - l = 0
+    prob.u[S.U] = A[S.U] @ x + s_uA           # -A x - s_u + u = 0
+    prob.lx = np.full(n, -np.inf); prob.ux = np.full(n, np.inf)
+    prob.lx[S.Lx] = x[S.Lx] - s_lx
+    prob.ux[S.Ux] = x[S.Ux] + s_ux
+    # penalty term (1/2mu)||Cx-b||^2 with lam_e = -(Cx - b)/mu
+    prob.b = prob.C @ x + mu * lam_e
+    # Lagrangian gradient: Hx + p + C^T(Cx-b)/mu - A^T lam_l + A^T lam_u - lam_lx + lam_ux = 0
+    g = np.zeros(n)
+    g += -A[S.L].T @ lam_lA + A[S.U].T @ lam_uA
+    g[S.Lx] -= lam_lx
+    g[S.Ux] += lam_ux
+    prob.p = -(prob.Hmul(x) + prob.C.T @ (-lam_e) + g)
+    st = O.State(x, lam_e, lam_lA, lam_uA, lam_lx, lam_ux, s_lA, s_uA, s_lx, s_ux)
+    res = O.residuals(prob, st, mu)
+    assert O.stacked_norm(res) < 1e-12
+    d, sol, rhs = O.newton_direction(prob, st, mu)
+    assert np.abs(rhs).max() < 1e-12 and np.abs(sol).max() < 1e-10
+
+
+# ------------------------------------------------- eliminations (P2, P3, P1)
+@pytest.mark.parametrize("seed,sparse_a", [(0, False), (1, True), (2, False), (3, True)])
+def test_doubly_augmented_matches_full_newton_system(seed, sparse_a):
+    """The 10-block system of eq. (7), solved by LU, and the Cholesky solve of
+    eq. (9) followed by recovery give the same full direction at an arbitrary
+    interior state (pins every sign of eqs. (8)-(9) and of the recovery)."""
+    rng = np.random.default_rng(100 + seed)
+    prob = general(seed, a_sparse=sparse_a)
+    st = random_state(prob, rng, spread=0.5)
+    mu = 0.7
+    res = O.residuals(prob, st, mu)
+    d1, _, _ = O.newton_direction(prob, st, mu, res)
+    d2 = O.full_newton_direction(prob, st, mu, res)
+    for f in d1.__dataclass_fields__:
+        a, b = getattr(d1, f), getattr(d2, f)
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-9 * max(1, np.abs(b).max(initial=0))), f
+
+
+def test_schur_complement_direction_matches():
+    """(Q + B^T D^-1 B) dx = r1 + B^T D^-1 r2 is the Schur complement of D in K."""
+    rng = np.random.default_rng(7)
+    prob = general(4)
+    st = random_state(prob, rng)
+    d1, _, _ = O.newton_direction(prob, st, 0.2)
+    d2 = O.schur_direction(prob, st, 0.2)
+    assert rel(d2.dx, d1.dx) < 1e-10
+    assert rel(d2.dlam_lA, d1.dlam_lA) < 1e-9
+
+
+def test_kkt_is_spd_along_the_iterates():
+    """Eq. (9) is SPD for convex QPs (Section 3.1): at every iterate."""
+    prob = general(5)
+    st = O.initial_point(prob)
+    mu = 1.0
+    for _ in range(12):
+        res = O.residuals(prob, st, mu)
+        Q, B, D, r1, r2, _ = O.reduced_system(prob, st, res, mu)
+        K, _ = O.doubly_augmented(Q, B, D, r1, r2)
+        assert np.allclose(K, K.T)
+        assert np.linalg.eigvalsh(K).min() > 0
+        d, _, _ = O.newton_direction(prob, st, mu, res)
+        ax, al = O.step_lengths(st, d)
+        st = O.take_step(st, d, ax, al)
+        mu *= 0.5
+
+
+# ----------------------------------------------- operator, Jacobi (P4, P5)
+@pytest.mark.parametrize("h_kind", ["dense", "lowrank"])
+def test_matrix_free_operator_and_jacobi(h_kind):
+    rng = np.random.default_rng(11)
+    prob = general(6, a_sparse=True, h_kind=h_kind)
+    st = random_state(prob, rng)
+    mu = 0.3
+    res = O.residuals(prob, st, mu)
+    Q, B, D, r1, r2, _ = O.reduced_system(prob, st, res, mu)
+    K, rhs = O.doubly_augmented(Q, B, D, r1, r2)
+    N = K.shape[0]
+    cols = np.stack([O.kkt_matvec(prob, st, mu, e) for e in np.eye(N)], axis=1)
+    assert np.allclose(cols, K, rtol=1e-12, atol=1e-12 * np.abs(K).max())
+    assert np.allclose(O.jacobi_diagonal(prob, st, mu), np.diag(K), rtol=1e-12)
+    rhs2, _ = O.newton_rhs_doubly(prob, st, mu)
+    assert np.allclose(rhs2, rhs, rtol=1e-12, atol=1e-12 * np.abs(rhs).max())
+    u, v = rng.standard_normal(N), rng.standard_normal(N)
+    Ku, Kv = O.kkt_matvec(prob, st, mu, u), O.kkt_matvec(prob, st, mu, v)
+    assert abs(u @ Kv - v @ Ku) < 1e-11 * abs(u @ Kv)
+    assert v @ Kv > 0
+
+
+def test_pcg_agrees_with_cholesky():
+    """Jacobi PCG at tolerance 1e-7 (Section 5.1) reproduces the direct solve to
+    within the residual bound kappa(K) * tol."""
+    rng = np.random.default_rng(3)
+    prob = general(7, n=30, m=25, me=2, mg=10)
+    st = random_state(prob, rng, 0.7)
+    mu = 0.05
+    res = O.residuals(prob, st, mu)
+    Q, B, D, r1, r2, _ = O.reduced_system(prob, st, res, mu)
+    K, rhs = O.doubly_augmented(Q, B, D, r1, r2)
+    dg = np.diag(K)
+    x, it, conv, rr = pcg(lambda v: K @ v, rhs, dg, 1e-10, 5000)
+    assert conv and rr <= 1e-10
+    xd = np.linalg.solve(K, rhs)
+    Kj = K / np.sqrt(np.outer(dg, dg))
+    kappa = np.linalg.cond(Kj)
+    assert rel(x, xd) <= 10 * kappa * 1e-10
+
+
+# ------------------------------------------------------- IPM invariants (P7)
+def test_primal_residual_contracts_by_one_minus_alpha():
+    """Slack steps come from the primal rows, so each primal residual block
+    scales by exactly (1 - alpha_x) per step (to rounding)."""
+    prob = general(8)
+    st = O.initial_point(prob)
+    mu = 1.0
+    for _ in range(6):
+        res = O.residuals(prob, st, mu)
+        d, _, _ = O.newton_direction(prob, st, mu, res)
+        ax, al = O.step_lengths(st, d)
+        st = O.take_step(st, d, ax, al)
+        res2 = O.residuals(prob, st, mu)
+        for a, b in ((res.rlA, res2.rlA), (res.ruA, res2.ruA), (res.rlx, res2.rlx), (res.rux, res2.rux)):
+            assert np.allclose(b, (1 - ax) * a, atol=1e-12 * (1 + np.abs(a).max(initial=0)))
+
+
+def test_ratio_test_reaches_fraction_of_boundary():
+    """Eq. (10): when alpha < 1 the step reaches exactly gamma of the way to the
+    nearest zero; all entries stay positive."""
+    rng = np.random.default_rng(9)
+    prob = general(9)
+    for _ in range(5):
+        st = random_state(prob, rng)
+        d, _, _ = O.newton_direction(prob, st, 0.5)
+        ax, al = O.step_lengths(st, d, 0.99)
+        s = np.concatenate([st.s_lA, st.s_uA, st.s_lx, st.s_ux])
+        ds = np.concatenate([d.ds_lA, d.ds_uA, d.ds_lx, d.ds_ux])
+        assert np.all(s + ax * ds > 0)
+        if ax < 1:
+            assert abs(np.min(s + (ax / 0.99) * ds)) < 1e-12 * np.abs(s).max()
+        lam = np.concatenate([st.lam_lA, st.lam_uA, st.lam_lx, st.lam_ux])
+        dl = np.concatenate([d.dlam_lA, d.dlam_uA, d.dlam_lx, d.dlam_ux])
+        assert np.all(lam + al * dl > 0)
+        if al < 1:
+            assert abs(np.min(lam + (al / 0.99) * dl)) < 1e-12 * np.abs(lam).max()
+
+
+# ------------------------------------------------- closed forms (P8, P9, P10)
+def test_unconstrained_closed_form_and_iteration_count():
+    """No constraints: the first Newton step lands on x = -H^-1 p, and the
+    mu schedule 1 -> 1e-7 by repeated FP64 division ends after exactly 8
+    iterations (mu6 = 1.0000000000000002e-06 is not below 1e-6)."""
+    rng = np.random.default_rng(0)
+    n = 8
+    G = rng.standard_normal((n, n))
+    spec = W.QPSpec(n=n, c=rng.standard_normal(n), h_kind="dense", H=G.T @ G + np.eye(n))
+    prob = O.from_spec(spec)
+    r = O.solve(prob)
+    assert r.status == "converged" and r.iterations == 8
+    assert np.allclose(r.state.x, -np.linalg.solve(spec.H, spec.c), rtol=1e-12)
+    mus = [e["mu"] for e in r.log]
+    assert mus[0] == 1.0 and mus[6] == 1.0000000000000002e-06 and mus[7] < 1e-6
+
+
+def test_box_only_separable_closed_form():
+    rng = np.random.default_rng(1)
+    n = 12
+    h = rng.uniform(0.5, 2, n)
+    c = rng.standard_normal(n) * 3
+    lx, ux = -np.ones(n), np.ones(n)
+    prob = O.from_spec(W.QPSpec(n=n, c=c, h_kind="dense", H=np.diag(h), lx=lx, ux=ux))
+    r = O.solve(prob)
+    assert r.status == "converged"
+    assert np.abs(r.state.x - np.clip(-c / h, lx, ux)).max() < 1e-5
+
+
+def test_equality_only_penalty_closed_form():
+    """Only C x = b: the penalty-barrier system is linear, so one Newton step
+    solves (H + C^T C / mu) x = -p + C^T b / mu at mu = 1; as mu -> 0 the
+    iterate tends to the solution of the equality-constrained QP."""
+    rng = np.random.default_rng(2)
+    n, me = 9, 3
+    G = rng.standard_normal((n, n))
+    H = G.T @ G + np.eye(n)
+    c = rng.standard_normal(n)
+    C = rng.standard_normal((me, n))
+    b = rng.standard_normal(me)
+    prob = O.from_spec(W.QPSpec(n=n, c=c, h_kind="dense", H=H, C=C, b=b))
+    r = O.solve(prob, O.IPMOptions(max_iter=1))
+    x1 = np.linalg.solve(H + C.T @ C / 1.0, -c + C.T @ b / 1.0)
+    assert np.allclose(r.state.x, x1, rtol=1e-10)
+    r = O.solve(prob)
+    kkt = np.linalg.solve(np.block([[H, C.T], [C, np.zeros((me, me))]]), np.concatenate([-c, b]))
+    assert np.abs(r.state.x - kkt[:n]).max() < 1e-5
+
+
+# ---------------------------------------------- whole-oracle pins (P11, P12)
+@pytest.mark.parametrize("seed", range(6))
+def test_ipm_matches_brute_force_active_set(seed):
+    spec = W.random_bounded_qp(seed, 5, 4, seed % 2, 3)
+    prob = O.from_spec(spec)
+    r = O.solve(prob)
+    assert r.status == "converged"
+    x, f, act = O.brute_force_qp(prob)
+    assert np.abs(r.state.x - x).max() < 1e-4
+    assert abs(r.objective - f) <= 1e-5 * max(1.0, abs(f))
+
+
+def test_ipm_matches_scipy_trust_constr():
+    spec = W.random_bounded_qp(21, 10, 8, 2, 5)
+    prob = O.from_spec(spec)
+    r = O.solve(prob)
+    H = prob.Hdense()
+    cons = [so.LinearConstraint(prob.A, prob.l, prob.u),
+            so.LinearConstraint(prob.C, prob.b, prob.b)]
+    sol = so.minimize(lambda x: 0.5 * x @ H @ x + prob.p @ x, np.zeros(prob.n),
+                      jac=lambda x: H @ x + prob.p, hess=lambda x: H,
+                      method="trust-constr", constraints=cons,
+                      bounds=so.Bounds(prob.lx, prob.ux),
+                      options=dict(gtol=1e-10, xtol=1e-12, maxiter=5000))
+    assert abs(r.objective - sol.fun) < 1e-4 * max(1, abs(sol.fun))
+    assert np.abs(r.state.x - sol.x).max() < 1e-3
+
+
+def test_initial_point_is_strictly_interior():
+    prob = general(12)
+    st = O.initial_point(prob)
+    for f in ("lam_lA", "lam_uA", "lam_lx", "lam_ux", "s_lA", "s_uA", "s_lx", "s_ux"):
+        assert np.all(getattr(st, f) > 0)
+    res = O.residuals(prob, st, 1.0)
+    assert np.allclose(res.rlx, 0) and np.allclose(res.rux, 0)
+
+
+def test_tiny_dense_generator_construction():
+    """Ax0 - b = u >= 0.1 (x0 strictly feasible) and lambda_min(H) >= 1e-3."""
+    spec = W.tiny_dense(0)
+    prob = O.from_spec(spec)
+    assert np.all(spec.A @ spec.extra["x0"] - spec.lA >= 0.1 - 1e-9)
+    assert np.linalg.eigvalsh(prob.Hdense()).min() >= 1e-3 - 1e-9
+
+
+# --------------------------------------------------------- Woodbury (P17)
+def test_woodbury_direction_matches_dense():
+    spec = W.svm_qp(5, 300, 8)
+    prob = O.from_spec(spec)
+    rng = np.random.default_rng(4)
+    st = random_state(prob, rng, 0.5)
+    st.lam_e = rng.standard_normal(1)
+    d1, _, _ = O.newton_direction(prob, st, 0.01)
+    d2 = O.woodbury_direction(prob, st, 0.01, h0=spec.h0, U=spec.U, wd=spec.wd)
+    assert rel(d2.dx, d1.dx) < 1e-8
+    assert rel(d2.dlam_lx, d1.dlam_lx) < 1e-8
+
+
+# ---------------------------------------------------------- adjoint (P15/16)
+def test_adjoint_unconstrained_closed_form():
+    rng = np.random.default_rng(5)
+    n = 6
+    G = rng.standard_normal((n, n))
+    H = G.T @ G + np.eye(n)
+    prob = O.from_spec(W.QPSpec(n=n, c=rng.standard_normal(n), h_kind="dense", H=H))
+    r = O.solve(prob)
+    g = rng.standard_normal(n)
+    out = O.adjoint_gradients(prob, r.state, r.mu, g)
+    assert np.allclose(out["c"], -np.linalg.solve(H, g), rtol=1e-10)
+
+
+def test_adjoint_matches_central_differences_on_centered_solves():
+    """dL/d(c, l, u, b, w) from the adjoint agree with central differences of
+    the exactly centered solution x*(theta) at fixed mu (h = 1e-6)."""
+    rng = np.random.default_rng(6)
+    base = W.rt_qp(4, 60, 8, 0.3, 8, maxdose=0.3)
+    base.c = np.random.default_rng(4).standard_normal(base.n) * 0.5
+    xref = rng.uniform(0, 1, base.n)
+    prob = O.from_spec(base)
+    r = O.solve(prob)
+    mu = r.mu
+    st = O.center(prob, r.state, mu)
+    L = lambda x: float(np.sum((x - xref) ** 2))
+    out = O.adjoint_gradients(prob, st, mu, 2 * (st.x - xref), P=base.P, w=base.w, d=base.d)
+    # the case has active max-dose rows and active x >= 0 bounds
+    assert (st.s_uA < 1e-4).sum() >= 2 and (st.s_lx < 1e-4).sum() >= 2
+    assert np.linalg.norm(out["u"]) > 1e-2
+
+    def solve_at(spec):
+        p2 = O.from_spec(spec)
+        return O.center(p2, st, mu).x
+
+    import copy
+    h = 1e-6
+    for name, grad in (("c", out["c"]), ("uA", out["u"]), ("w", out["w"])):
+        v = rng.standard_normal(grad.size)
+        v /= np.linalg.norm(v)
+        sp_, sm_ = copy.deepcopy(base), copy.deepcopy(base)
+        setattr(sp_, name, getattr(base, name) + h * v)
+        setattr(sm_, name, getattr(base, name) - h * v)
+        fd = (L(solve_at(sp_)) - L(solve_at(sm_))) / (2 * h)
+        assert abs(fd - grad @ v) <= 1e-4 * max(1e-3, abs(fd)), (name, fd, grad @ v)
