@@ -1,0 +1,256 @@
+/*
+ * qpk: a primal-dual interior point method for convex QPs whose Newton
+ * systems are solved by Jacobi-preconditioned conjugate gradients on the
+ * doubly augmented KKT matrix, for one AMD MI355X (gfx950).
+ *
+ * Method: Liu, Fredriksson, Markidis, "Krylov Solvers for Interior Point
+ * Methods with Applications in Radiation Therapy and Support Vector Machines"
+ * (arXiv 2308.00637).  Section and equation numbers below refer to it:
+ *   eq. (1)  the QP; eq. (3) perturbed optimality conditions (residuals);
+ *   eq. (7)  the full Newton system; eq. (8) the 2x2 augmented system;
+ *   eq. (9)  the doubly augmented SPD system solved by PCG (Section 3.1);
+ *   eq. (10) the ratio test; Algorithm 1 the IPM loop (Section 3.2).
+ *
+ * Problem solved (eq. (1), variable bounds kept apart as in Section 3.1):
+ *     min 1/2 x^T H x + c^T x   s.t.  lA <= A x <= uA,  C x = b,  lx <= x <= ux
+ * Infinite bound entries (+-INFINITY) mean "no bound on that side"; only finite
+ * sides carry a slack/multiplier pair.
+ *
+ * Conventions
+ *  - Every function returns a qp_status; 0 is success, negative values are
+ *    errors.  No C++ exception crosses this boundary.  After an error,
+ *    qp_last_error(h) returns a message (valid until the next call on h).
+ *  - qp_desc pointers are HOST pointers.  qp_create copies and converts all of
+ *    them into library-owned device buffers; the caller may free them on
+ *    return.
+ *  - Every other double* argument is a DEVICE pointer (e.g. a torch tensor's
+ *    data_ptr()) unless documented as host.  Device arguments must not alias
+ *    each other.  All device work is ordered on the stream given to qp_create
+ *    (or qp_set_stream); functions that return host values synchronise it.
+ *  - Layouts of the iterate (device, float64):
+ *      x   : n
+ *      lam : me + 2m + 2n = [lam_e (me) | lam_lA (m) | lam_uA (m) | lam_lx (n) | lam_ux (n)]
+ *      s   : 2m + 2n      = [s_lA (m) | s_uA (m) | s_lx (n) | s_ux (n)]
+ *    Entries of absent (infinite) sides are ignored on input and written as 0.
+ *  - Layout of a doubly augmented vector (eq. (9)), N = n + me + 2m:
+ *      [x-part (n) | lam_e-part (me) | lam_lA-part (m) | lam_uA-part (m)]
+ *    Rows of absent sides are identity rows of K (their entries stay 0).
+ *  - Layout of the residual stack (eq. (3)/(7) right-hand side), 5n + me + 4m:
+ *      [r_H (n) | r_e (me) | r_lA (m) | r_uA (m) | r_lx (n) | r_ux (n) |
+ *       r_c1 (m) | r_c2 (m) | r_c3 (n) | r_c4 (n)]
+ *  - A handle is not thread-safe; calls on one handle must be serialised.
+ */
+#ifndef QPK_H
+#define QPK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qp_handle_s* qp_handle;
+
+typedef enum {
+  QP_OK = 0,
+  QP_ERR_ARG = -1,         /* invalid argument or problem data */
+  QP_ERR_ALLOC = -2,       /* device or host allocation failed */
+  QP_ERR_HIP = -3,         /* a HIP runtime call failed */
+  QP_ERR_NOT_SPD = -4,     /* PCG met p^T K p <= 0: H not convex or state broken */
+  QP_ERR_NUMERIC = -5,     /* NaN or Inf met in a reduction */
+  QP_ERR_STATE = -6,       /* call made in the wrong state (e.g. backward before solve) */
+  QP_ERR_UNSUPPORTED = -7  /* valid request this build does not implement */
+} qp_status;
+
+typedef enum { QP_H_DENSE = 0, QP_H_LOWRANK = 1, QP_H_PTWP = 2 } qp_h_kind;
+typedef enum { QP_A_NONE = 0, QP_A_DENSE = 1, QP_A_CSR = 2 } qp_a_kind;
+typedef enum {
+  QP_PREC_FP64 = 0,   /* every operation in float64 */
+  QP_PREC_FP32 = 1,   /* PCG matvec values stored and accumulated in float32 */
+  QP_PREC_BF16 = 2    /* PCG matvec values stored in bfloat16, float32 accumulate */
+} qp_precision;
+
+/* Problem description (all pointers HOST, read only during qp_create). */
+typedef struct {
+  int64_t n;                 /* variables, >= 1 */
+  int64_t m;                 /* general rows of A, >= 0 */
+  int64_t me;                /* equality rows of C, 0 <= me <= 64 */
+  int32_t h_kind;            /* qp_h_kind */
+  /* QP_H_DENSE: H symmetric, n*n row-major. */
+  const double* H;
+  /* QP_H_LOWRANK: H = diag(h0) + U diag(wd) U^T, the quasi-Newton form
+   * H0 + U W U^T of Section 2.2 (and the linear-kernel SVM Gram matrix).
+   * U is n*k row-major; 1 <= k <= 1024. */
+  int64_t k;
+  const double* h0;          /* n */
+  const double* U;           /* n*k */
+  const double* wd;          /* k */
+  /* QP_H_PTWP: H = P^T diag(w) P with P sparse (p_rows x n, CSR), and the
+   * objective's linear term becomes c - P^T diag(w) d, i.e. the objective is
+   * 1/2 sum_v w_v (P_v x - d_v)^2 + c^T x up to a constant. */
+  int64_t p_rows;
+  const int64_t* p_rowptr;   /* p_rows + 1 */
+  const int32_t* p_col;      /* nnz, each in [0, n) */
+  const double* p_val;       /* nnz */
+  const double* p_w;         /* p_rows, w_v > 0 */
+  const double* p_d;         /* p_rows, or NULL for zeros */
+  const double* c;           /* n */
+  int32_t a_kind;            /* qp_a_kind; QP_A_NONE requires m == 0 */
+  const double* A;           /* QP_A_DENSE: m*n row-major */
+  const int64_t* a_rowptr;   /* QP_A_CSR: m + 1 */
+  const int32_t* a_col;
+  const double* a_val;
+  const double* lA;          /* m, entries may be -INFINITY */
+  const double* uA;          /* m, entries may be +INFINITY; lA <= uA */
+  const double* C;           /* me*n row-major */
+  const double* b;           /* me */
+  const double* lx;          /* n or NULL (all -INFINITY) */
+  const double* ux;          /* n or NULL (all +INFINITY); lx < ux where both finite */
+  int32_t precision;         /* qp_precision */
+} qp_desc;
+
+/* PCG settings (Section 5.1: tolerance 1e-7 on the unpreconditioned residual,
+ * relative to ||rhs||_2; at most 5000 iterations; start from 0). */
+typedef struct {
+  double tol;                /* default 1e-7 */
+  int32_t maxit;             /* default 5000 */
+  int32_t check_every;       /* iterations between host polls of the stop flag; default 8 */
+  int32_t rr_period;         /* mixed precision only: recompute r = rhs - K x in float64
+                              * and restart every rr_period iterations; default 50, 0 = off */
+} pcg_options;
+
+typedef struct {
+  int32_t iterations;
+  int32_t converged;         /* 1 if ||r|| <= tol ||rhs|| */
+  int32_t status;            /* qp_status of the solve */
+  double rel_residual;       /* final ||rhs - K sol|| / ||rhs|| (float64 operator) */
+  double rhs_norm;
+} pcg_info;
+
+/* Algorithm 1 settings.  gamma of eq. (10); mu is divided by mu_div when the
+ * stacked residual norm falls below mu, and the solve returns when that
+ * happens with mu < mu_tol (Section 3.2). */
+typedef struct {
+  double gamma;              /* 0.99 */
+  double mu0;                /* 1.0 */
+  double mu_tol;             /* 1e-6 */
+  double mu_div;             /* 10 */
+  int32_t max_iter;          /* 200 */
+  int32_t warm_start;        /* 0: default start point; 1: current handle state and mu */
+  pcg_options pcg;
+  /* optional per-iteration log (HOST arrays of log_capacity entries each, or NULL) */
+  int32_t log_capacity;
+  double* log_mu;
+  double* log_rnorm;
+  double* log_primal;
+  double* log_dual;
+  double* log_compl;
+  double* log_alpha_x;
+  double* log_alpha_lam;
+  int32_t* log_cg_iters;
+  double* log_cg_relres;
+} ipm_options;
+
+typedef enum { QP_IPM_CONVERGED = 0, QP_IPM_MAX_ITER = 1 } qp_ipm_result;
+
+typedef struct {
+  int32_t result;            /* qp_ipm_result */
+  int32_t iterations;        /* IPM iterations taken */
+  int64_t total_cg_iters;
+  int32_t cg_maxiter_hits;   /* Newton steps whose PCG stopped at maxit */
+  double mu_final;
+  double rnorm;              /* stacked residual norm at the returned point */
+  double primal, dual, compl_; /* infeasibilities of Section 5.2 */
+  double objective;          /* 1/2 x^T H x + (linear term)^T x */
+  double time_ms;            /* wall time of the solve (stream-synchronised) */
+  double pcg_time_ms;        /* part of it inside PCG */
+} ipm_info;
+
+void qp_default_pcg_options(pcg_options* o);
+void qp_default_ipm_options(ipm_options* o);
+const char* qp_status_string(int32_t status);
+const char* qp_last_error(qp_handle h);
+
+/* Create a handle: validates d (QP_ERR_ARG on n <= 0, lA > uA, lx >= ux,
+ * non-finite data, bad CSR), copies it into device layouts, and precomputes
+ * the constant parts (diag(H), the linear term).  stream is a hipStream_t
+ * (NULL = default stream).  On error *out is NULL. */
+qp_status qp_create(const qp_desc* d, void* stream, qp_handle* out);
+void qp_destroy(qp_handle h);
+qp_status qp_set_stream(qp_handle h, void* stream);
+
+/* Sizes of the device layouts above. */
+qp_status qp_sizes(qp_handle h, int64_t* n_x, int64_t* n_lam, int64_t* n_s,
+                   int64_t* n_kkt, int64_t* n_res);
+
+/* Iterate I/O.  qp_set_state copies a caller iterate (QP_ERR_ARG if a present
+ * slack or multiplier is <= 0 or not finite).  qp_init_state loads the
+ * default starting point: x at the middle of two-sided bounds, one unit inside
+ * one-sided ones, 0 if free; bound slacks exact; row slacks max(distance, 1);
+ * inequality multipliers 1; lam_e 0. */
+qp_status qp_set_state(qp_handle h, const double* x, const double* lam,
+                       const double* s, double mu);
+qp_status qp_get_state(qp_handle h, double* x, double* lam, double* s,
+                       double* mu /* host, may be NULL */);
+qp_status qp_init_state(qp_handle h, double mu);
+
+/* Residual stack of eq. (3)/(7) at the current state and mu (step a1).
+ * r: device, 5n+me+4m, or NULL.  norms: HOST double[4] =
+ * {stacked ||r||_2, primal, dual, complementarity} (Section 5.2), or NULL. */
+qp_status qp_residuals(qp_handle h, double* r, double* norms);
+
+/* Right-hand side of eq. (9) and diag(K) (the Jacobi preconditioner of
+ * Section 3.1) at the current state (steps a2, a3).  Device, N each; either
+ * may be NULL. */
+qp_status qp_newton_rhs(qp_handle h, double* rhs, double* jacobi_diag);
+
+/* y = K v for the doubly augmented K of eq. (9) at the current state, applied
+ * matrix-free as in Section 3.2 (step a4, float64 operator).  Device, N each. */
+qp_status qp_kkt_matvec(qp_handle h, const double* v, double* y);
+
+/* Solve K sol = rhs by Jacobi PCG at the current state (step a5).  rhs, sol:
+ * device, N.  o may be NULL for defaults; info (host) may be NULL.  Returns
+ * QP_ERR_NOT_SPD if a curvature p^T K p <= 0 is met. */
+qp_status kkt_pcg_solve(qp_handle h, const double* rhs, double* sol,
+                        const pcg_options* o, pcg_info* info);
+
+/* Full Newton direction at the current state (steps a1-a6): residuals,
+ * eq. (9) by PCG, then the eliminated unknowns (slack steps from the primal
+ * rows of eq. (7), bound-multiplier steps from its complementarity rows).
+ * dx (n), dlam (me+2m+2n), ds (2m+2n): device, iterate layouts. */
+qp_status qp_newton_direction(qp_handle h, const pcg_options* o, double* dx,
+                              double* dlam, double* ds, pcg_info* info);
+
+/* Ratio test of eq. (10) (step a7) for a direction in iterate layout.
+ * alpha_x / alpha_lam: HOST. */
+qp_status qp_step_lengths(qp_handle h, const double* dlam, const double* ds,
+                          double gamma, double* alpha_x, double* alpha_lam);
+
+/* x += alpha_x dx, s += alpha_x ds, every multiplier += alpha_lam dlam
+ * (Algorithm 1, step a8). */
+qp_status qp_take_step(qp_handle h, const double* dx, const double* dlam,
+                       const double* ds, double alpha_x, double alpha_lam);
+
+/* Algorithm 1 (steps a1-a9).  x, lam, s: device outputs in iterate layouts,
+ * each may be NULL (the result stays in the handle, see qp_get_state).
+ * o may be NULL for defaults; info (host) must not be NULL. */
+qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam,
+                    double* s, ipm_info* info);
+
+/* Adjoint of the solution (not in the paper): for a loss L(x*) with gradient
+ * grad_x (device, n), returns dL/dc (n), dL/dlA (m), dL/duA (m), dL/db (me)
+ * and, for QP_H_PTWP, dL/dw (p_rows), each a device pointer or NULL.  It
+ * differentiates the perturbed optimality conditions at the returned point
+ * and mu, which needs one PCG solve with the same K as the last Newton step:
+ * K u = (grad_x, 0); dL/dc = -u_x, dL/dlA = -u_lamlA, dL/duA = u_lamuA,
+ * dL/db = -u_lame, dL/dw_v = -(P_v u_x)(P_v x - d_v).  Entries for absent
+ * sides are 0.  QP_ERR_STATE unless ipm_solve has completed on this handle. */
+qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c,
+                      double* grad_lA, double* grad_uA, double* grad_b,
+                      double* grad_w, const pcg_options* o, pcg_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPK_H */

@@ -1,0 +1,1023 @@
+// Host side of libqpk: the C ABI of include/qpk.h.  Builds the device layouts
+// once (qp_create), then drives the kernels of qpk_kernels.hip for each step
+// of Algorithm 1 (Section 3.2).  Host code only launches kernels, reads back a
+// few scalars per IPM iteration and polls one stop flag during PCG; all
+// arithmetic of the method runs on the GPU.
+#include "qpk_internal.h"
+#include "../../include/qpk.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace qpk;
+
+struct qp_handle_s {
+  std::string err;
+  hipStream_t st = nullptr;
+  int n = 0, m = 0, me = 0, k = 0, p_rows = 0, h_kind = 0, prec = 0, vk = VK_F64;
+  int nRP = 0;
+  int64_t nnz_rp = 0, nnz_xs = 0;
+  // operators (float64 always; *_lo: reduced-precision copies for the PCG matvec)
+  int32_t *rp_rowptr = nullptr, *rp_col = nullptr;
+  double* rp_val = nullptr;
+  void* rp_lo = nullptr;
+  int32_t *xs_rowptr = nullptr, *xs_seg1 = nullptr, *xs_seg2 = nullptr, *xs_col = nullptr;
+  double* xs_val = nullptr;
+  void* xs_lo = nullptr;
+  double* U = nullptr;
+  void* U_lo = nullptr;
+  double *wd = nullptr, *h0 = nullptr, *Cm = nullptr, *b = nullptr, *c = nullptr, *c_eff = nullptr;
+  double *lA = nullptr, *uA = nullptr, *lx = nullptr, *ux = nullptr, *pw = nullptr, *pd = nullptr;
+  double* diagH = nullptr;
+  bool has_xs = false, has_ts = false;
+  // iterate
+  double *x = nullptr, *lam = nullptr, *s = nullptr;
+  double mu = 1.0;
+  bool solved = false;
+  bool res_valid = false, sys_valid = false;
+  // work
+  double *res = nullptr, *rhs = nullptr, *jdiag = nullptr, *dl = nullptr, *qdiag = nullptr;
+  double *wA_mv = nullptr, *wA_res = nullptr, *wA_rhs = nullptr, *jw = nullptr;
+  double *we_mv = nullptr, *we_res = nullptr, *we_rhs = nullptr, *te = nullptr, *g = nullptr, *u = nullptr;
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *tmp = nullptr;
+  double *dir = nullptr, *ds_w = nullptr;   // dir = [dx | dlam] (n + me + 2m + 2n)
+  double* arhs = nullptr;                    // adjoint right-hand side
+  double *part = nullptr, *ts_part = nullptr, *sc = nullptr;
+  int* fl = nullptr;
+  double* hsc = nullptr;  // pinned host copy of sc
+  int* hfl = nullptr;     // pinned host copy of fl
+  int lpr_r = 16, lpr_x = 64, g_r = 1, g_x = 1, g_vec = 1, g_ts = 1, ts_chunk = 1, g_n = 1, g_ra = 1;
+  std::vector<void*> allocs;
+  ~qp_handle_s() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hsc) (void)hipHostFree(hsc);
+    if (hfl) (void)hipHostFree(hfl);
+  }
+  int64_t N() const { return (int64_t)n + me + 2 * (int64_t)m; }
+  int64_t nlam() const { return (int64_t)me + 2 * (int64_t)m + 2 * (int64_t)n; }
+  int64_t ns() const { return 2 * (int64_t)m + 2 * (int64_t)n; }
+  int64_t nres() const { return 5 * (int64_t)n + me + 4 * (int64_t)m; }
+};
+
+#define HIPCHK(expr)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      h->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+      return QP_ERR_HIP;                                                        \
+    }                                                                           \
+  } while (0)
+
+#define CHK(expr)                      \
+  do {                                 \
+    qp_status s_ = (expr);             \
+    if (s_ != QP_OK) return s_;        \
+  } while (0)
+
+static qp_status dalloc(qp_handle h, void** p, size_t bytes) {
+  *p = nullptr;
+  hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+  if (e != hipSuccess) {
+    h->err = std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e);
+    return QP_ERR_ALLOC;
+  }
+  h->allocs.push_back(*p);
+  return QP_OK;
+}
+
+template <typename T>
+static qp_status dalloc_t(qp_handle h, T** p, int64_t count) {
+  return dalloc(h, reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(count, 0));
+}
+
+template <typename T>
+static qp_status upload(qp_handle h, T** p, const T* src, int64_t count) {
+  CHK(dalloc_t(h, p, count));
+  if (count > 0) HIPCHK(hipMemcpyAsync(*p, src, sizeof(T) * count, hipMemcpyHostToDevice, h->st));
+  return QP_OK;
+}
+
+static inline uint16_t to_bf16(double v) {
+  float f = (float)v;
+  uint32_t bits;
+  std::memcpy(&bits, &f, 4);
+  if ((bits & 0x7f800000u) == 0x7f800000u) return (uint16_t)(bits >> 16);  // inf / nan
+  const uint32_t rounding = 0x7fffu + ((bits >> 16) & 1u);                 // nearest even
+  return (uint16_t)((bits + rounding) >> 16);
+}
+
+static qp_status upload_lo(qp_handle h, void** p, const std::vector<double>& v) {
+  if (h->vk == VK_F32) {
+    std::vector<float> f(v.size());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+    float* d;
+    CHK(upload(h, &d, f.data(), (int64_t)f.size()));
+    HIPCHK(hipStreamSynchronize(h->st));
+    *p = d;
+  } else {
+    std::vector<uint16_t> f(v.size());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = to_bf16(v[i]);
+    uint16_t* d;
+    CHK(upload(h, &d, f.data(), (int64_t)f.size()));
+    HIPCHK(hipStreamSynchronize(h->st));
+    *p = d;
+  }
+  return QP_OK;
+}
+
+static int pow2_clamp(double v, int lo, int hi) {
+  int p = lo;
+  while (p < hi && p * 2 <= v) p *= 2;
+  return p;
+}
+
+static int grid_cap(int64_t items, int per_block, int cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+// ------------------------------------------------------------ arg builders
+static VecArgs vec_args(qp_handle h) {
+  VecArgs a{};
+  a.n = h->n; a.m = h->m; a.me = h->me; a.N = (int32_t)h->N();
+  a.x = h->x; a.lam = h->lam; a.s = h->s;
+  a.lA = h->lA; a.uA = h->uA; a.lx = h->lx; a.ux = h->ux; a.b = h->b;
+  a.mu = h->mu; a.res = h->res; a.rhs = h->rhs; a.jdiag = h->jdiag; a.dl = h->dl;
+  a.wA = h->wA_rhs; a.jw = h->jw; a.we = h->we_rhs;
+  a.dx = h->dir; a.dlam = h->dir + h->n; a.ds = h->ds_w; a.dlam_w = h->dir + h->n;
+  a.gamma = 0.99; a.part = h->part; a.sc = h->sc; a.fl = h->fl;
+  return a;
+}
+
+static RowArgs row_args(qp_handle h, bool lo) {
+  RowArgs a{};
+  a.p_rows = h->p_rows; a.m = h->m; a.n = h->n; a.me = h->me;
+  a.rowptr = h->rp_rowptr; a.col = h->rp_col;
+  a.val = lo ? h->rp_lo : (const void*)h->rp_val;
+  a.w = h->pw; a.d = h->pd; a.u = h->u; a.lA = h->lA; a.uA = h->uA;
+  a.lam = h->lam; a.s = h->s; a.mu = h->mu; a.res = h->res;
+  return a;
+}
+
+static ColArgs col_args(qp_handle h, bool lo) {
+  ColArgs a{};
+  a.n = h->n; a.me = h->me; a.m = h->m; a.p_rows = h->p_rows; a.k = h->k;
+  a.rowptr = h->xs_rowptr; a.seg1 = h->xs_seg1; a.seg2 = h->xs_seg2; a.col = h->xs_col;
+  a.val = h->has_xs ? (lo ? h->xs_lo : (const void*)h->xs_val) : nullptr;
+  a.use_hx = 1; a.use_pt = 1; a.use_at = 1;
+  a.U = lo ? h->U_lo : (const void*)h->U;
+  a.g = h->g; a.Cm = h->Cm; a.qdiag = h->qdiag;
+  a.c = h->c_eff; a.h0 = h->h0; a.lam = h->lam; a.s = h->s; a.lx = h->lx; a.ux = h->ux;
+  a.mu = h->mu; a.diagH = h->diagH; a.wd = h->wd; a.w = h->pw;
+  return a;
+}
+
+static TsArgs ts_args(qp_handle h, bool lo, const double* v) {
+  TsArgs a{};
+  a.n = h->n; a.k = h->k; a.me = h->me;
+  a.U = lo ? h->U_lo : (const void*)h->U;
+  a.Cm = h->Cm; a.v = v; a.part = h->ts_part; a.chunk = h->ts_chunk;
+  return a;
+}
+
+static TsFinishArgs tsf_args(qp_handle h) {
+  TsFinishArgs a{};
+  a.n = h->n; a.k = h->k; a.me = h->me; a.grid = h->g_ts;
+  a.part = h->ts_part; a.wd = h->wd; a.g = h->g; a.te = h->te;
+  a.b = h->b; a.lam = h->lam; a.mu = h->mu; a.res = h->res;
+  return a;
+}
+
+// ---------------------------------------------------------------- steps
+// Step a1: residual stack at (x, lam, s, mu) and its norms (into sc).
+static qp_status run_residuals(qp_handle h) {
+  if (h->has_ts) {
+    HIPCHK(launch_ts_reduce(VK_F64, ts_args(h, false, h->x), h->g_ts, h->st));
+    TsFinishArgs f = tsf_args(h);
+    f.we = h->we_res;
+    f.partout = h->part + P_NTS_RE * kGridMax;
+    HIPCHK(launch_ts_finish(TS_RESID, f, h->st));
+  }
+  if (h->nRP > 0) {
+    RowArgs a = row_args(h, false);
+    a.r0 = 0; a.r1 = h->nRP; a.v = h->x; a.wA = h->wA_res; a.resw = h->res;
+    a.part0 = h->part + P_NR_PRIMAL * kGridMax;
+    a.part1 = h->part + P_NR_COMPL * kGridMax;
+    HIPCHK(launch_rowpass(R_RESID, VK_F64, h->lpr_r, a, h->g_r, h->st));
+  }
+  ColArgs c = col_args(h, false);
+  c.src_hx = h->x; c.src_pt = h->u; c.src_at = h->wA_res; c.we = h->we_res; c.v = h->x;
+  c.res = h->res;
+  c.part0 = h->part + P_NX_DUAL * kGridMax;
+  c.part1 = h->part + P_NX_PRIMAL * kGridMax;
+  c.part2 = h->part + P_NX_COMPL * kGridMax;
+  HIPCHK(launch_colpass(X_RESID, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  HIPCHK(launch_finish_norms(vec_args(h), h->nRP > 0 ? h->g_r : 0, h->g_x, h->st));
+  h->res_valid = true;
+  return QP_OK;
+}
+
+// Steps a2, a3: D, the eq. (9) right-hand side, diag(K), Q's diagonal.
+static qp_status run_system(qp_handle h) {
+  if (!h->res_valid) CHK(run_residuals(h));
+  VecArgs v = vec_args(h);
+  HIPCHK(launch_rhs_lam(v, h->st));
+  ColArgs c = col_args(h, false);
+  c.use_hx = 0; c.use_pt = 0; c.use_at = 1;
+  c.src_at = h->wA_rhs; c.src_at2 = h->jw; c.we = h->we_rhs;
+  c.res_in = h->res; c.rhs = h->rhs; c.jdiag = h->jdiag; c.qdiag_out = h->qdiag;
+  HIPCHK(launch_colpass(X_RHS, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  h->sys_valid = true;
+  return QP_OK;
+}
+
+static qp_status prepare(qp_handle h) {
+  if (!h->sys_valid) CHK(run_system(h));
+  return QP_OK;
+}
+
+// Step a4: y = K v (v, y: K-vectors).  lo selects the reduced-precision
+// operator copies.  done/bump: PCG early exit and iteration counter.
+static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, const int* done,
+                            int* bump) {
+  const int vk = lo ? h->vk : VK_F64;
+  if (h->has_ts) {
+    TsArgs t = ts_args(h, lo, v);
+    t.done = done;
+    HIPCHK(launch_ts_reduce(vk, t, h->g_ts, h->st));
+    TsFinishArgs f = tsf_args(h);
+    f.we = h->we_mv; f.vl = v + h->n; f.yl = y + h->n;
+    f.partout = h->part + P_DOT_TS * kGridMax; f.done = done;
+    HIPCHK(launch_ts_finish(TS_MATVEC, f, h->st));
+  }
+  if (h->nRP > 0) {
+    RowArgs a = row_args(h, lo);
+    a.r0 = 0; a.r1 = h->nRP; a.v = v; a.vl = v + h->n; a.dl = h->dl; a.yl = y + h->n;
+    a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
+    HIPCHK(launch_rowpass(R_MATVEC, vk, h->lpr_r, a, h->g_r, h->st));
+  }
+  ColArgs c = col_args(h, lo);
+  c.src_hx = v; c.src_pt = h->u; c.src_at = h->wA_mv; c.we = h->we_mv; c.v = v; c.y = y;
+  c.part0 = h->part + P_DOT_X * kGridMax; c.done = done; c.bump = bump;
+  HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_x, h->st));
+  return QP_OK;
+}
+
+static CgArgs cg_args(qp_handle h, const double* rhs, double* sol, const pcg_options& o) {
+  CgArgs a{};
+  a.N = (int32_t)h->N(); a.n = h->n;
+  a.x = sol; a.r = h->cg_r; a.z = h->cg_z; a.p = h->cg_p; a.q = h->cg_q;
+  a.rhs = rhs; a.jdiag = h->jdiag; a.part = h->part; a.fl = h->fl; a.sc = h->sc;
+  a.g_vec = h->g_vec; a.g_r = h->nRP > 0 ? h->g_r : 0; a.g_x = h->g_x; a.has_ts = h->has_ts;
+  a.tol = o.tol; a.maxit = o.maxit;
+  return a;
+}
+
+static qp_status read_back(qp_handle h) {
+  HIPCHK(hipMemcpyAsync(h->hsc, h->sc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(h->hfl, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+// Step a5: Jacobi PCG (needs prepare()).  Also reports the true relative
+// residual ||rhs - K sol|| / ||rhs|| with the float64 operator.
+static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_options& o,
+                         pcg_info* info) {
+  CgArgs a = cg_args(h, rhs, sol, o);
+  HIPCHK(launch_cg_init(a, h->st));
+  const bool lo = h->vk != VK_F64;
+  const int check = std::max(1, o.check_every);
+  int it = 0;
+  bool done = false;
+  CHK(read_back(h));
+  done = h->hfl[F_DONE] != 0;
+  while (!done && it < o.maxit) {
+    const int chunk = std::min(check, o.maxit - it);
+    for (int c = 0; c < chunk; ++c, ++it) {
+      if (lo && o.rr_period > 0 && it > 0 && it % o.rr_period == 0) {
+        CHK(run_matvec(h, false, sol, h->tmp, h->fl + F_DONE, nullptr));
+        HIPCHK(launch_cg_restart(a, h->tmp, h->st));
+      }
+      CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT));
+      HIPCHK(launch_cg_update(a, h->st));
+      HIPCHK(launch_cg_pupdate(a, h->st));
+    }
+    HIPCHK(hipMemcpyAsync(h->hfl, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    done = h->hfl[F_DONE] != 0;
+  }
+  // true residual with the float64 operator
+  CHK(run_matvec(h, false, sol, h->tmp, nullptr, nullptr));
+  HIPCHK(launch_sqdiff(rhs, h->tmp, h->N(), h->part + P_CHK * kGridMax, h->g_vec, h->st));
+  HIPCHK(launch_finish_sum(h->part + P_CHK * kGridMax, h->g_vec, h->sc + S_RELRES, h->st));
+  CHK(read_back(h));
+  const int status = h->hfl[F_STATUS];
+  pcg_info inf{};
+  inf.iterations = h->hfl[F_ITERS];
+  inf.converged = status == 1;
+  inf.rhs_norm = h->hsc[S_RHSNORM];
+  inf.status = QP_OK;
+  if (status == QP_ERR_NOT_SPD_CODE) inf.status = QP_ERR_NOT_SPD;
+  if (status == QP_ERR_NUMERIC_CODE) inf.status = QP_ERR_NUMERIC;
+  if (status == 0) inf.iterations = o.maxit;
+  inf.rel_residual = inf.rhs_norm > 0.0 ? std::sqrt(h->hsc[S_RELRES]) / inf.rhs_norm : 0.0;
+  if (info) *info = inf;
+  if (inf.status == QP_ERR_NOT_SPD) {
+    h->err = "PCG met a non-positive curvature p^T K p (H not convex, or the iterate is broken)";
+    return QP_ERR_NOT_SPD;
+  }
+  if (inf.status == QP_ERR_NUMERIC) {
+    h->err = "PCG met a NaN or Inf";
+    return QP_ERR_NUMERIC;
+  }
+  return QP_OK;
+}
+
+// Step a6: recovery of ds and the bound multipliers' steps, and the ratio
+// test of step a7 (alphas into sc).
+static qp_status run_recover(qp_handle h, double gamma) {
+  if (h->m > 0) {
+    RowArgs a = row_args(h, false);
+    a.r0 = h->p_rows; a.r1 = h->nRP; a.v = h->dir; a.dlam = h->dir + h->n; a.ds = h->ds_w;
+    a.part0 = h->part + P_MIN_S_R * kGridMax; a.part1 = h->part + P_MIN_L_R * kGridMax;
+    HIPCHK(launch_rowpass(R_RECOVER, VK_F64, h->lpr_r, a, h->g_ra, h->st));
+  }
+  VecArgs v = vec_args(h);
+  v.gamma = gamma;
+  HIPCHK(launch_recover_x(v, h->g_n, h->st));
+  HIPCHK(launch_finish_ratio(v, h->m > 0 ? h->g_ra : 0, h->g_n, h->st));
+  return QP_OK;
+}
+
+static qp_status run_objective(qp_handle h, double* out) {
+  if (h->p_rows > 0) {
+    RowArgs a = row_args(h, false);
+    a.r0 = 0; a.r1 = h->p_rows; a.v = h->x;
+    HIPCHK(launch_rowpass(R_PU, VK_F64, h->lpr_r, a, h->g_r, h->st));
+  }
+  if (h->k > 0) {
+    HIPCHK(launch_ts_reduce(VK_F64, ts_args(h, false, h->x), h->g_ts, h->st));
+    TsFinishArgs f = tsf_args(h);
+    f.we = h->we_mv;
+    HIPCHK(launch_ts_finish(TS_GONLY, f, h->st));
+  }
+  ColArgs c = col_args(h, false);
+  c.use_at = 0; c.src_hx = h->x; c.src_pt = h->u; c.v = h->x; c.part0 = h->part + P_OBJ * kGridMax;
+  HIPCHK(launch_colpass(X_OBJ, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  HIPCHK(launch_finish_sum(h->part + P_OBJ * kGridMax, h->g_x, h->sc + S_OBJ, h->st));
+  CHK(read_back(h));
+  *out = h->hsc[S_OBJ];
+  return QP_OK;
+}
+
+static qp_status run_init_state(qp_handle h, double mu) {
+  h->mu = mu;
+  VecArgs v = vec_args(h);
+  HIPCHK(launch_init_x(v, grid_cap(std::max(h->n, h->me), kBlock, kGridMax), h->st));
+  if (h->m > 0) {
+    RowArgs a = row_args(h, false);
+    a.r0 = h->p_rows; a.r1 = h->nRP; a.v = h->x; a.ds = h->s; a.yl = h->lam;
+    HIPCHK(launch_rowpass(R_INIT, VK_F64, h->lpr_r, a, h->g_ra, h->st));
+  }
+  h->res_valid = h->sys_valid = false;
+  h->solved = false;
+  return QP_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+void qp_default_pcg_options(pcg_options* o) {
+  if (!o) return;
+  o->tol = 1e-7;
+  o->maxit = 5000;
+  o->check_every = 8;
+  o->rr_period = 50;
+}
+
+void qp_default_ipm_options(ipm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->gamma = 0.99;
+  o->mu0 = 1.0;
+  o->mu_tol = 1e-6;
+  o->mu_div = 10.0;
+  o->max_iter = 200;
+  o->warm_start = 0;
+  qp_default_pcg_options(&o->pcg);
+}
+
+const char* qp_status_string(int32_t s) {
+  switch (s) {
+    case QP_OK: return "ok";
+    case QP_ERR_ARG: return "invalid argument";
+    case QP_ERR_ALLOC: return "allocation failed";
+    case QP_ERR_HIP: return "HIP runtime error";
+    case QP_ERR_NOT_SPD: return "KKT matrix not positive definite";
+    case QP_ERR_NUMERIC: return "NaN or Inf encountered";
+    case QP_ERR_STATE: return "call not valid in the current state";
+    case QP_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+static thread_local std::string g_create_error;
+
+const char* qp_last_error(qp_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+static qp_status create_impl(qp_handle h, const qp_desc* d) {
+  const int64_t n = d->n, m = d->m, me = d->me;
+  auto bad = [&](const std::string& msg) { h->err = msg; return QP_ERR_ARG; };
+  if (n <= 0 || m < 0 || me < 0 || me > 64) return bad("need n >= 1, m >= 0, 0 <= me <= 64");
+  if (d->precision < QP_PREC_FP64 || d->precision > QP_PREC_BF16) return bad("bad precision");
+  if (!d->c) return bad("c is required");
+  if (me > 0 && (!d->C || !d->b)) return bad("C and b are required when me > 0");
+  if (m > 0 && (!d->lA || !d->uA)) return bad("lA and uA are required when m > 0");
+  if (m > 0 && d->a_kind != QP_A_DENSE && d->a_kind != QP_A_CSR) return bad("m > 0 needs A");
+  if (m == 0 && d->a_kind != QP_A_NONE && d->a_kind != QP_A_DENSE && d->a_kind != QP_A_CSR)
+    return bad("bad a_kind");
+  h->n = (int)n; h->m = (int)m; h->me = (int)me; h->h_kind = d->h_kind; h->prec = d->precision;
+  h->vk = d->precision == QP_PREC_FP32 ? VK_F32 : d->precision == QP_PREC_BF16 ? VK_BF16 : VK_F64;
+  auto finite_all = [](const double* p, int64_t cnt) {
+    for (int64_t i = 0; i < cnt; ++i) if (!std::isfinite(p[i])) return false;
+    return true;
+  };
+  if (!finite_all(d->c, n)) return bad("c has non-finite entries");
+  // bounds
+  std::vector<double> lx(n, -INFINITY), ux(n, INFINITY);
+  if (d->lx) std::copy(d->lx, d->lx + n, lx.begin());
+  if (d->ux) std::copy(d->ux, d->ux + n, ux.begin());
+  for (int64_t j = 0; j < n; ++j) {
+    if (std::isnan(lx[j]) || std::isnan(ux[j]) || lx[j] == INFINITY || ux[j] == -INFINITY)
+      return bad("invalid variable bound at " + std::to_string(j));
+    if (std::isfinite(lx[j]) && std::isfinite(ux[j]) && !(lx[j] < ux[j]))
+      return bad("need lx < ux where both are finite (variable " + std::to_string(j) + ")");
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    const double l = d->lA[i], u = d->uA[i];
+    if (std::isnan(l) || std::isnan(u) || l == INFINITY || u == -INFINITY || l > u)
+      return bad("invalid row bounds at row " + std::to_string(i));
+  }
+  if (me > 0 && (!finite_all(d->C, me * n) || !finite_all(d->b, me))) return bad("C or b non-finite");
+
+  // Hessian pieces
+  std::vector<double> diagH(n, 0.0), h0(n, 0.0);
+  int64_t k = 0;
+  int64_t p_rows = 0;
+  std::vector<int64_t> prp;
+  const int32_t* pcol = nullptr;
+  const double* pval = nullptr;
+  if (d->h_kind == QP_H_DENSE) {
+    if (!d->H || !finite_all(d->H, n * n)) return bad("dense H missing or non-finite");
+    for (int64_t j = 0; j < n; ++j) diagH[j] = d->H[j * n + j];
+  } else if (d->h_kind == QP_H_LOWRANK) {
+    k = d->k;
+    if (k < 1 || k > 1024 || !d->U || !d->wd || !d->h0) return bad("low-rank H needs 1 <= k <= 1024, h0, U, wd");
+    if (!finite_all(d->U, n * k) || !finite_all(d->wd, k) || !finite_all(d->h0, n))
+      return bad("low-rank H has non-finite entries");
+    for (int64_t j = 0; j < n; ++j) h0[j] = d->h0[j];
+    diagH = h0;
+  } else if (d->h_kind == QP_H_PTWP) {
+    p_rows = d->p_rows;
+    if (p_rows < 1 || !d->p_rowptr || !d->p_col || !d->p_val || !d->p_w) return bad("P^T W P needs P and w");
+    if (d->p_rowptr[0] != 0) return bad("P rowptr[0] must be 0");
+    for (int64_t v = 0; v < p_rows; ++v)
+      if (d->p_rowptr[v + 1] < d->p_rowptr[v]) return bad("P rowptr not monotone");
+    const int64_t nnz = d->p_rowptr[p_rows];
+    for (int64_t q = 0; q < nnz; ++q)
+      if (d->p_col[q] < 0 || d->p_col[q] >= n || !std::isfinite(d->p_val[q])) return bad("bad P entry");
+    for (int64_t v = 0; v < p_rows; ++v)
+      if (!(d->p_w[v] > 0.0) || !std::isfinite(d->p_w[v]) || (d->p_d && !std::isfinite(d->p_d[v])))
+        return bad("P weights must be positive and finite");
+    prp.assign(d->p_rowptr, d->p_rowptr + p_rows + 1);
+    pcol = d->p_col;
+    pval = d->p_val;
+  } else {
+    return bad("bad h_kind");
+  }
+  h->k = (int)k;
+  h->p_rows = (int)p_rows;
+  h->nRP = (int)(p_rows + m);
+
+  // A as CSR rows (dense A keeps its nonzeros)
+  std::vector<int64_t> arp(m + 1, 0);
+  std::vector<int32_t> acol;
+  std::vector<double> aval;
+  if (m > 0) {
+    if (d->a_kind == QP_A_DENSE) {
+      if (!d->A || !finite_all(d->A, m * n)) return bad("dense A missing or non-finite");
+      for (int64_t i = 0; i < m; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+          const double v = d->A[i * n + j];
+          if (v != 0.0) { acol.push_back((int32_t)j); aval.push_back(v); }
+        }
+        arp[i + 1] = (int64_t)acol.size();
+      }
+    } else {
+      if (!d->a_rowptr || !d->a_col || !d->a_val || d->a_rowptr[0] != 0) return bad("bad CSR A");
+      for (int64_t i = 0; i < m; ++i) {
+        if (d->a_rowptr[i + 1] < d->a_rowptr[i]) return bad("A rowptr not monotone");
+        for (int64_t q = d->a_rowptr[i]; q < d->a_rowptr[i + 1]; ++q) {
+          if (d->a_col[q] < 0 || d->a_col[q] >= n || !std::isfinite(d->a_val[q])) return bad("bad A entry");
+          acol.push_back(d->a_col[q]);
+          aval.push_back(d->a_val[q]);
+        }
+        arp[i + 1] = (int64_t)acol.size();
+      }
+    }
+  }
+  const int64_t pnnz = p_rows > 0 ? prp[p_rows] : 0;
+  const int64_t annz = (int64_t)acol.size();
+  const int64_t hnnz = d->h_kind == QP_H_DENSE ? n * n : 0;
+  if (pnnz + annz >= INT32_MAX || pnnz + annz + hnnz >= INT32_MAX)
+    return bad("operators exceed 2^31 stored entries");
+  h->nnz_rp = pnnz + annz;
+
+  // Row side RP = [P rows; A rows]
+  std::vector<int32_t> rrp(h->nRP + 1), rcol(h->nnz_rp);
+  std::vector<double> rval(h->nnz_rp);
+  for (int64_t v = 0; v < p_rows; ++v) {
+    rrp[v] = (int32_t)prp[v];
+    for (int64_t q = prp[v]; q < prp[v + 1]; ++q) { rcol[q] = pcol[q]; rval[q] = pval[q]; }
+  }
+  for (int64_t i = 0; i <= m; ++i) rrp[p_rows + i] = (int32_t)(pnnz + arp[i]);
+  for (int64_t q = 0; q < annz; ++q) { rcol[pnnz + q] = acol[q]; rval[pnnz + q] = aval[q]; }
+
+  // Column side XS: per variable j, [H row j | column j of P | column j of A]
+  std::vector<int64_t> cnt_h(n, 0), cnt_p(n, 0), cnt_a(n, 0);
+  if (hnnz) for (int64_t j = 0; j < n; ++j) cnt_h[j] = n;
+  for (int64_t q = 0; q < pnnz; ++q) cnt_p[pcol[q]]++;
+  for (int64_t q = 0; q < annz; ++q) cnt_a[acol[q]]++;
+  std::vector<int32_t> xrp(n + 1), xs1(n), xs2(n);
+  int64_t acc = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    xrp[j] = (int32_t)acc; acc += cnt_h[j];
+    xs1[j] = (int32_t)acc; acc += cnt_p[j];
+    xs2[j] = (int32_t)acc; acc += cnt_a[j];
+  }
+  xrp[n] = (int32_t)acc;
+  h->nnz_xs = acc;
+  std::vector<int32_t> xcol(acc);
+  std::vector<double> xval(acc);
+  {
+    std::vector<int64_t> fp(n), fa(n);
+    for (int64_t j = 0; j < n; ++j) {
+      if (hnnz) for (int64_t i = 0; i < n; ++i) { xcol[xrp[j] + i] = (int32_t)i; xval[xrp[j] + i] = d->H[j * n + i]; }
+      fp[j] = xs1[j];
+      fa[j] = xs2[j];
+    }
+    for (int64_t v = 0; v < p_rows; ++v)
+      for (int64_t q = prp[v]; q < prp[v + 1]; ++q) {
+        const int64_t j = pcol[q];
+        xcol[fp[j]] = (int32_t)v; xval[fp[j]] = pval[q]; fp[j]++;
+      }
+    for (int64_t i = 0; i < m; ++i)
+      for (int64_t q = arp[i]; q < arp[i + 1]; ++q) {
+        const int64_t j = acol[q];
+        xcol[fa[j]] = (int32_t)i; xval[fa[j]] = aval[q]; fa[j]++;
+      }
+  }
+  h->has_xs = acc > 0;
+  h->has_ts = k > 0 || me > 0;
+
+  // Launch shapes
+  const double avg_r = h->nRP > 0 ? (double)h->nnz_rp / h->nRP : 0.0;
+  const double avg_x = (double)acc / n + (double)k;
+  h->lpr_r = pow2_clamp(avg_r / 4.0, 4, 64);
+  h->lpr_x = pow2_clamp(avg_x / 4.0, 4, 64);
+  h->g_r = grid_cap((int64_t)h->nRP * h->lpr_r, kBlock, kGridMax);
+  h->g_ra = grid_cap((int64_t)std::max<int64_t>(m, 1) * h->lpr_r, kBlock, kGridMax);
+  h->g_x = grid_cap(n * (int64_t)h->lpr_x, kBlock, kGridMax);
+  h->g_vec = grid_cap(h->N(), kBlock, 512);
+  h->g_n = grid_cap(n, kBlock, kGridMax);
+  h->g_ts = (int)std::max<int64_t>(1, std::min<int64_t>(kGridMax, (n + 63) / 64));
+  h->ts_chunk = (int)((n + h->g_ts - 1) / h->g_ts);
+
+  // Device buffers
+  CHK(upload(h, &h->rp_rowptr, rrp.data(), (int64_t)rrp.size()));
+  CHK(upload(h, &h->rp_col, rcol.data(), (int64_t)rcol.size()));
+  CHK(upload(h, &h->rp_val, rval.data(), (int64_t)rval.size()));
+  CHK(upload(h, &h->xs_rowptr, xrp.data(), (int64_t)xrp.size()));
+  CHK(upload(h, &h->xs_seg1, xs1.data(), (int64_t)xs1.size()));
+  CHK(upload(h, &h->xs_seg2, xs2.data(), (int64_t)xs2.size()));
+  CHK(upload(h, &h->xs_col, xcol.data(), (int64_t)xcol.size()));
+  CHK(upload(h, &h->xs_val, xval.data(), (int64_t)xval.size()));
+  if (k > 0) {
+    CHK(upload(h, &h->U, d->U, n * k));
+    CHK(upload(h, &h->wd, d->wd, k));
+  } else {
+    CHK(dalloc_t(h, &h->U, 1));
+    CHK(dalloc_t(h, &h->wd, 1));
+  }
+  if (h->vk != VK_F64) {
+    CHK(upload_lo(h, &h->rp_lo, rval));
+    CHK(upload_lo(h, &h->xs_lo, xval));
+    if (k > 0) {
+      std::vector<double> uv(d->U, d->U + n * k);
+      CHK(upload_lo(h, &h->U_lo, uv));
+    } else {
+      h->U_lo = h->U;
+    }
+  }
+  CHK(upload(h, &h->h0, h0.data(), n));
+  CHK(upload(h, &h->c, d->c, n));
+  CHK(dalloc_t(h, &h->c_eff, n));
+  CHK(upload(h, &h->lx, lx.data(), n));
+  CHK(upload(h, &h->ux, ux.data(), n));
+  if (m > 0) {
+    CHK(upload(h, &h->lA, d->lA, m));
+    CHK(upload(h, &h->uA, d->uA, m));
+  } else {
+    CHK(dalloc_t(h, &h->lA, 1));
+    CHK(dalloc_t(h, &h->uA, 1));
+  }
+  if (me > 0) {
+    CHK(upload(h, &h->Cm, d->C, me * n));
+    CHK(upload(h, &h->b, d->b, me));
+  } else {
+    CHK(dalloc_t(h, &h->Cm, 1));
+    CHK(dalloc_t(h, &h->b, 1));
+  }
+  if (p_rows > 0) {
+    CHK(upload(h, &h->pw, d->p_w, p_rows));
+    if (d->p_d) CHK(upload(h, &h->pd, d->p_d, p_rows));
+  } else {
+    CHK(dalloc_t(h, &h->pw, 1));
+  }
+  CHK(upload(h, &h->diagH, diagH.data(), n));
+
+  const int64_t N = h->N();
+  CHK(dalloc_t(h, &h->x, n));
+  CHK(dalloc_t(h, &h->lam, h->nlam()));
+  CHK(dalloc_t(h, &h->s, h->ns()));
+  CHK(dalloc_t(h, &h->res, h->nres()));
+  CHK(dalloc_t(h, &h->rhs, N));
+  CHK(dalloc_t(h, &h->jdiag, N));
+  CHK(dalloc_t(h, &h->dl, me + 2 * m));
+  CHK(dalloc_t(h, &h->qdiag, n));
+  CHK(dalloc_t(h, &h->wA_mv, m));
+  CHK(dalloc_t(h, &h->wA_res, m));
+  CHK(dalloc_t(h, &h->wA_rhs, m));
+  CHK(dalloc_t(h, &h->jw, m));
+  CHK(dalloc_t(h, &h->we_mv, me));
+  CHK(dalloc_t(h, &h->we_res, me));
+  CHK(dalloc_t(h, &h->we_rhs, me));
+  CHK(dalloc_t(h, &h->te, me));
+  CHK(dalloc_t(h, &h->g, k));
+  CHK(dalloc_t(h, &h->u, p_rows));
+  CHK(dalloc_t(h, &h->cg_r, N));
+  CHK(dalloc_t(h, &h->cg_z, N));
+  CHK(dalloc_t(h, &h->cg_p, N));
+  CHK(dalloc_t(h, &h->cg_q, N));
+  CHK(dalloc_t(h, &h->tmp, N));
+  CHK(dalloc_t(h, &h->arhs, N));
+  CHK(dalloc_t(h, &h->dir, n + h->nlam()));
+  CHK(dalloc_t(h, &h->ds_w, h->ns()));
+  CHK(dalloc_t(h, &h->part, (int64_t)P_COUNT * kGridMax));
+  CHK(dalloc_t(h, &h->ts_part, (int64_t)h->g_ts * (k + me)));
+  CHK(dalloc_t(h, &h->sc, S_COUNT));
+  CHK(dalloc_t(h, &h->fl, F_COUNT));
+  HIPCHK(hipMemsetAsync(h->part, 0, sizeof(double) * P_COUNT * kGridMax, h->st));
+  HIPCHK(hipMemsetAsync(h->dir, 0, sizeof(double) * (n + h->nlam()), h->st));
+  HIPCHK(hipMemsetAsync(h->ds_w, 0, sizeof(double) * h->ns(), h->st));
+  HIPCHK(hipMemsetAsync(h->fl, 0, sizeof(int) * F_COUNT, h->st));
+  HIPCHK(hipMemsetAsync(h->sc, 0, sizeof(double) * S_COUNT, h->st));
+  {
+    hipError_t e1 = hipHostMalloc((void**)&h->hsc, sizeof(double) * S_COUNT, hipHostMallocDefault);
+    hipError_t e2 = hipHostMalloc((void**)&h->hfl, sizeof(int) * F_COUNT, hipHostMallocDefault);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      h->err = "hipHostMalloc failed";
+      return QP_ERR_ALLOC;
+    }
+  }
+
+  // Constant parts: diag(H) += diag(P^T W P) + sum_l wd_l U_jl^2; c_eff = c - P^T W d.
+  if (p_rows > 0 || k > 0) {
+    ColArgs c = col_args(h, false);
+    c.use_hx = 0; c.use_at = 0; c.use_pt = p_rows > 0;
+    c.v = h->diagH; c.y = h->diagH;
+    HIPCHK(launch_colpass(X_DIAGH, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  }
+  if (p_rows > 0 && h->pd) {
+    ColArgs c = col_args(h, false);
+    c.use_hx = 0; c.use_at = 0; c.use_pt = 1; c.src_pt = h->pd; c.c = h->c; c.y = h->c_eff;
+    HIPCHK(launch_colpass(X_CEFF, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  } else {
+    HIPCHK(launch_copy(h->c, h->c_eff, n, 1.0, h->st));
+  }
+  CHK(run_init_state(h, 1.0));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_create(const qp_desc* d, void* stream, qp_handle* out) {
+  if (!out) return QP_ERR_ARG;
+  *out = nullptr;
+  if (!d) return QP_ERR_ARG;
+  qp_handle h = new (std::nothrow) qp_handle_s();
+  if (!h) return QP_ERR_ALLOC;
+  h->st = (hipStream_t)stream;
+  qp_status s;
+  try {
+    s = create_impl(h, d);
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    s = QP_ERR_ALLOC;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    s = QP_ERR_ARG;
+  }
+  if (s != QP_OK) {
+    // the handle is gone: keep the message for qp_last_error(NULL)
+    g_create_error = h->err;
+    delete h;
+    return s;
+  }
+  *out = h;
+  return QP_OK;
+}
+
+void qp_destroy(qp_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->st);
+  delete h;
+}
+
+qp_status qp_set_stream(qp_handle h, void* stream) {
+  if (!h) return QP_ERR_ARG;
+  h->st = (hipStream_t)stream;
+  return QP_OK;
+}
+
+qp_status qp_sizes(qp_handle h, int64_t* n_x, int64_t* n_lam, int64_t* n_s, int64_t* n_kkt,
+                   int64_t* n_res) {
+  if (!h) return QP_ERR_ARG;
+  if (n_x) *n_x = h->n;
+  if (n_lam) *n_lam = h->nlam();
+  if (n_s) *n_s = h->ns();
+  if (n_kkt) *n_kkt = h->N();
+  if (n_res) *n_res = h->nres();
+  return QP_OK;
+}
+
+qp_status qp_set_state(qp_handle h, const double* x, const double* lam, const double* s, double mu) {
+  if (!h) return QP_ERR_ARG;
+  if (!x || !lam || !s) { h->err = "x, lam and s are required"; return QP_ERR_ARG; }
+  if (!(mu > 0.0) || !std::isfinite(mu)) { h->err = "mu must be positive"; return QP_ERR_ARG; }
+  HIPCHK(hipMemcpyAsync(h->x, x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(h->lam, lam, sizeof(double) * h->nlam(), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(h->s, s, sizeof(double) * h->ns(), hipMemcpyDeviceToDevice, h->st));
+  h->mu = mu;
+  h->res_valid = h->sys_valid = false;
+  h->solved = false;
+  VecArgs v = vec_args(h);
+  const int grid = grid_cap(h->nlam(), kBlock, kGridMax);
+  HIPCHK(launch_check_state(v, grid, h->st));
+  HIPCHK(launch_finish_sum(h->part + P_CHK * kGridMax, grid, h->sc + S_RELRES, h->st));
+  CHK(read_back(h));
+  if (h->hsc[S_RELRES] != 0.0) {
+    h->err = "state has non-positive or non-finite slacks/multipliers (" +
+             std::to_string((long long)h->hsc[S_RELRES]) + " entries)";
+    return QP_ERR_ARG;
+  }
+  return QP_OK;
+}
+
+qp_status qp_get_state(qp_handle h, double* x, double* lam, double* s, double* mu) {
+  if (!h) return QP_ERR_ARG;
+  if (x) HIPCHK(hipMemcpyAsync(x, h->x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->st));
+  if (lam) HIPCHK(hipMemcpyAsync(lam, h->lam, sizeof(double) * h->nlam(), hipMemcpyDeviceToDevice, h->st));
+  if (s) HIPCHK(hipMemcpyAsync(s, h->s, sizeof(double) * h->ns(), hipMemcpyDeviceToDevice, h->st));
+  if (mu) *mu = h->mu;
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_init_state(qp_handle h, double mu) {
+  if (!h) return QP_ERR_ARG;
+  if (!(mu > 0.0)) { h->err = "mu must be positive"; return QP_ERR_ARG; }
+  CHK(run_init_state(h, mu));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_residuals(qp_handle h, double* r, double* norms) {
+  if (!h) return QP_ERR_ARG;
+  CHK(run_residuals(h));
+  if (r) HIPCHK(hipMemcpyAsync(r, h->res, sizeof(double) * h->nres(), hipMemcpyDeviceToDevice, h->st));
+  CHK(read_back(h));
+  if (norms) {
+    norms[0] = h->hsc[S_NORM];
+    norms[1] = h->hsc[S_PRIMAL];
+    norms[2] = h->hsc[S_DUAL];
+    norms[3] = h->hsc[S_COMPL];
+  }
+  return QP_OK;
+}
+
+qp_status qp_newton_rhs(qp_handle h, double* rhs, double* jacobi_diag) {
+  if (!h) return QP_ERR_ARG;
+  CHK(prepare(h));
+  if (rhs) HIPCHK(hipMemcpyAsync(rhs, h->rhs, sizeof(double) * h->N(), hipMemcpyDeviceToDevice, h->st));
+  if (jacobi_diag)
+    HIPCHK(hipMemcpyAsync(jacobi_diag, h->jdiag, sizeof(double) * h->N(), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_kkt_matvec(qp_handle h, const double* v, double* y) {
+  if (!h || !v || !y) return QP_ERR_ARG;
+  CHK(prepare(h));
+  CHK(run_matvec(h, false, v, y, nullptr, nullptr));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+static pcg_options pcg_opts_or_default(const pcg_options* o) {
+  pcg_options d;
+  qp_default_pcg_options(&d);
+  if (!o) return d;
+  d = *o;
+  if (!(d.tol > 0.0)) d.tol = 1e-7;
+  if (d.maxit < 1) d.maxit = 5000;
+  if (d.check_every < 1) d.check_every = 8;
+  return d;
+}
+
+qp_status kkt_pcg_solve(qp_handle h, const double* rhs, double* sol, const pcg_options* o,
+                        pcg_info* info) {
+  if (!h || !rhs || !sol) return QP_ERR_ARG;
+  CHK(prepare(h));
+  const pcg_options po = pcg_opts_or_default(o);
+  pcg_info inf{};
+  qp_status s = run_pcg(h, rhs, sol, po, &inf);
+  if (info) *info = inf;
+  return s;
+}
+
+qp_status qp_newton_direction(qp_handle h, const pcg_options* o, double* dx, double* dlam,
+                              double* ds, pcg_info* info) {
+  if (!h) return QP_ERR_ARG;
+  CHK(prepare(h));
+  const pcg_options po = pcg_opts_or_default(o);
+  pcg_info inf{};
+  qp_status s = run_pcg(h, h->rhs, h->dir, po, &inf);
+  if (info) *info = inf;
+  if (s != QP_OK) return s;
+  CHK(run_recover(h, 0.99));
+  if (dx) HIPCHK(hipMemcpyAsync(dx, h->dir, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->st));
+  if (dlam)
+    HIPCHK(hipMemcpyAsync(dlam, h->dir + h->n, sizeof(double) * h->nlam(), hipMemcpyDeviceToDevice, h->st));
+  if (ds) HIPCHK(hipMemcpyAsync(ds, h->ds_w, sizeof(double) * h->ns(), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_step_lengths(qp_handle h, const double* dlam, const double* ds, double gamma,
+                          double* alpha_x, double* alpha_lam) {
+  if (!h || !dlam || !ds) return QP_ERR_ARG;
+  VecArgs v = vec_args(h);
+  v.gamma = gamma;
+  const int grid = grid_cap(h->ns(), kBlock, kGridMax);
+  HIPCHK(launch_ratio_given(v, dlam, ds, grid, h->st));
+  HIPCHK(launch_finish_ratio(v, 0, grid, h->st));
+  CHK(read_back(h));
+  if (alpha_x) *alpha_x = h->hsc[S_ALPHA_X];
+  if (alpha_lam) *alpha_lam = h->hsc[S_ALPHA_L];
+  return QP_OK;
+}
+
+qp_status qp_take_step(qp_handle h, const double* dx, const double* dlam, const double* ds,
+                       double alpha_x, double alpha_lam) {
+  if (!h || !dx || !dlam || !ds) return QP_ERR_ARG;
+  VecArgs v = vec_args(h);
+  HIPCHK(launch_update(v, dx, dlam, ds, nullptr, alpha_x, alpha_lam,
+                       grid_cap(h->nlam(), kBlock, kGridMax), h->st));
+  h->res_valid = h->sys_valid = false;
+  h->solved = false;
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, double* s,
+                    ipm_info* info) {
+  if (!h || !info) return QP_ERR_ARG;
+  ipm_options opt;
+  qp_default_ipm_options(&opt);
+  if (o) opt = *o;
+  const pcg_options po = pcg_opts_or_default(&opt.pcg);
+  if (!(opt.gamma > 0.0 && opt.gamma < 1.0) || !(opt.mu0 > 0.0) || !(opt.mu_div > 1.0) ||
+      opt.max_iter < 1) {
+    h->err = "invalid ipm_options";
+    return QP_ERR_ARG;
+  }
+  std::memset(info, 0, sizeof(*info));
+  HIPCHK(hipStreamSynchronize(h->st));
+  const auto t0 = std::chrono::steady_clock::now();
+  double pcg_ms = 0.0;
+  if (!opt.warm_start) CHK(run_init_state(h, opt.mu0));
+  h->res_valid = h->sys_valid = false;
+  h->solved = false;
+  int it = 0;
+  bool converged = false;
+  for (it = 1; it <= opt.max_iter; ++it) {
+    CHK(prepare(h));
+    const auto tp = std::chrono::steady_clock::now();
+    pcg_info pi{};
+    CHK(run_pcg(h, h->rhs, h->dir, po, &pi));
+    pcg_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
+    info->total_cg_iters += pi.iterations;
+    if (!pi.converged) info->cg_maxiter_hits++;
+    CHK(run_recover(h, opt.gamma));
+    VecArgs v = vec_args(h);
+    HIPCHK(launch_update(v, h->dir, h->dir + h->n, h->ds_w, h->sc + S_ALPHA_X, 0.0, 0.0,
+                         grid_cap(h->nlam(), kBlock, kGridMax), h->st));
+    h->res_valid = h->sys_valid = false;
+    CHK(run_residuals(h));
+    CHK(read_back(h));
+    const double nr = h->hsc[S_NORM];
+    if (!std::isfinite(nr)) {
+      h->err = "residual norm is not finite";
+      return QP_ERR_NUMERIC;
+    }
+    const int li = it - 1;
+    if (li < opt.log_capacity) {
+      if (opt.log_mu) opt.log_mu[li] = h->mu;
+      if (opt.log_rnorm) opt.log_rnorm[li] = nr;
+      if (opt.log_primal) opt.log_primal[li] = h->hsc[S_PRIMAL];
+      if (opt.log_dual) opt.log_dual[li] = h->hsc[S_DUAL];
+      if (opt.log_compl) opt.log_compl[li] = h->hsc[S_COMPL];
+      if (opt.log_alpha_x) opt.log_alpha_x[li] = h->hsc[S_ALPHA_X];
+      if (opt.log_alpha_lam) opt.log_alpha_lam[li] = h->hsc[S_ALPHA_L];
+      if (opt.log_cg_iters) opt.log_cg_iters[li] = pi.iterations;
+      if (opt.log_cg_relres) opt.log_cg_relres[li] = pi.rel_residual;
+    }
+    info->rnorm = nr;
+    info->primal = h->hsc[S_PRIMAL];
+    info->dual = h->hsc[S_DUAL];
+    info->compl_ = h->hsc[S_COMPL];
+    if (nr < h->mu) {
+      if (h->mu < opt.mu_tol) {
+        converged = true;
+        break;
+      }
+      h->mu = h->mu / opt.mu_div;
+      h->res_valid = h->sys_valid = false;
+    }
+  }
+  info->iterations = converged ? it : opt.max_iter;
+  info->result = converged ? QP_IPM_CONVERGED : QP_IPM_MAX_ITER;
+  info->mu_final = h->mu;
+  CHK(run_objective(h, &info->objective));
+  if (x) HIPCHK(hipMemcpyAsync(x, h->x, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->st));
+  if (lam) HIPCHK(hipMemcpyAsync(lam, h->lam, sizeof(double) * h->nlam(), hipMemcpyDeviceToDevice, h->st));
+  if (s) HIPCHK(hipMemcpyAsync(s, h->s, sizeof(double) * h->ns(), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  info->pcg_time_ms = pcg_ms;
+  h->solved = true;
+  return QP_OK;
+}
+
+qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c, double* grad_lA,
+                      double* grad_uA, double* grad_b, double* grad_w, const pcg_options* o,
+                      pcg_info* info) {
+  if (!h || !grad_x) return QP_ERR_ARG;
+  if (!h->solved) {
+    h->err = "qp_backward needs a completed ipm_solve on this handle";
+    return QP_ERR_STATE;
+  }
+  if (grad_w && h->p_rows == 0) {
+    h->err = "grad_w needs a P^T W P Hessian";
+    return QP_ERR_ARG;
+  }
+  CHK(prepare(h));
+  // adjoint right-hand side (grad_x, 0)
+  double* arhs = h->arhs;
+  HIPCHK(launch_fill(arhs, h->N(), 0.0, h->st));
+  HIPCHK(launch_copy(grad_x, arhs, h->n, 1.0, h->st));
+  pcg_options po = pcg_opts_or_default(o);
+  if (!o) po.tol = 1e-10;
+  double* usol = h->dir;  // the direction buffer is free after the solve
+  pcg_info inf{};
+  qp_status s = run_pcg(h, arhs, usol, po, &inf);
+  if (info) *info = inf;
+  if (s != QP_OK) return s;
+  HIPCHK(launch_grad_out(h->n, h->m, h->me, usol, h->lA, h->uA, grad_c, grad_lA, grad_uA, grad_b, h->st));
+  if (grad_w) {
+    RowArgs a = row_args(h, false);
+    a.r0 = 0; a.r1 = h->p_rows; a.v = usol; a.v2 = h->x; a.gw = grad_w;
+    HIPCHK(launch_rowpass(R_GRADW, VK_F64, h->lpr_r, a, h->g_r, h->st));
+  }
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,935 @@
+// Device kernels of libqpk for gfx950 (CDNA4, wave64).
+//
+// The doubly augmented matrix of eq. (9) (Section 3.1),
+//     K = [[Q + 2 B^T D^-1 B, B^T], [B, D]],  B = [C; A_L; -A_U],
+// is applied matrix-free (Section 3.2).  For a K-vector v = (v_x, v_e, v_l, v_u):
+//     t = B v_x,  y_lam = t + D v_lam,  w = 2 D^-1 t + v_lam,
+//     y_x = H v_x + q_b * v_x + B^T w.
+// Row i of A contributes t_i = A_i . v_x and then A_i^T (w_l,i - w_u,i) to y_x,
+// so the work splits into a row-side pass (one segmented dot per row of A, and
+// per row of P when H = P^T W P) and a column-side pass over the transposed
+// operators (one segmented dot per variable).  Every reduction below has a
+// fixed order (lane tree, then block tree, then blocks in index order), so a
+// run is bitwise reproducible.
+#include "qpk_internal.h"
+
+#include <math.h>
+
+namespace qpk {
+
+// ------------------------------------------------------------------ basics
+template <int VK> struct VT;
+template <> struct VT<VK_F64> { using T = double;   using Acc = double; };
+template <> struct VT<VK_F32> { using T = float;    using Acc = float; };
+template <> struct VT<VK_BF16> { using T = uint16_t; using Acc = float; };
+
+__device__ __forceinline__ double ldv(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldv(const uint16_t* p, int64_t i) {
+  return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
+}
+
+__device__ __forceinline__ bool has_lo(double l) { return l > -INFINITY; }
+__device__ __forceinline__ bool has_hi(double u) { return u < INFINITY; }
+
+template <int W, typename A>
+__device__ __forceinline__ A group_sum(A v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+// Sum over the block; the result is valid on thread 0.
+__device__ double block_sum(double v) {
+  __shared__ double sh[kBlock / 64];
+  v = group_sum<64>(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_min(double v) {
+  __shared__ double sh[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = INFINITY;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) r = fmin(r, sh[i]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// Sum of cnt partials, identical on every thread of the block.
+__device__ double sum_bcast(const double* p, int cnt) {
+  __shared__ double shb;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += kBlock) v += p[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) shb = v;
+  __syncthreads();
+  v = shb;
+  __syncthreads();
+  return v;
+}
+
+__device__ double min_bcast(const double* p, int cnt) {
+  __shared__ double shb;
+  double v = INFINITY;
+  for (int i = threadIdx.x; i < cnt; i += kBlock) v = fmin(v, p[i]);
+  v = block_min(v);
+  if (threadIdx.x == 0) shb = v;
+  __syncthreads();
+  v = shb;
+  __syncthreads();
+  return v;
+}
+
+// Offsets into the residual stack.
+struct ResOff {
+  int64_t rH, re, rlA, ruA, rlx, rux, rc1, rc2, rc3, rc4;
+  __device__ ResOff(int n, int m, int me) {
+    rH = 0; re = n; rlA = re + me; ruA = rlA + m; rlx = ruA + m; rux = rlx + n;
+    rc1 = rux + n; rc2 = rc1 + m; rc3 = rc2 + m; rc4 = rc3 + n;
+  }
+};
+
+// ------------------------------------------------------- row-side pass
+// One group of LPR lanes per row of RP (rows of P, then rows of A).
+template <int MODE, int VK, int LPR>
+__global__ __launch_bounds__(kBlock) void k_rowpass(RowArgs a) {
+  using T = typename VT<VK>::T;
+  using Acc = typename VT<VK>::Acc;
+  if (a.done && *a.done) return;
+  const T* __restrict__ val = static_cast<const T*>(a.val);
+  const int lane = threadIdx.x & (LPR - 1);
+  const int gid = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+  const int ng = gridDim.x * (kBlock / LPR);
+  const int n = a.n, m = a.m, me = a.me;
+  double acc0 = 0.0, acc1 = 0.0;
+  double mn0 = INFINITY, mn1 = INFINITY;
+  for (int row = a.r0 + gid; row < a.r1; row += ng) {
+    const int beg = a.rowptr[row], end = a.rowptr[row + 1];
+    Acc t = 0, t2 = 0;
+    for (int q = beg + lane; q < end; q += LPR) {
+      const int c = a.col[q];
+      const Acc vv = ldv(val, q);
+      t += vv * static_cast<Acc>(a.v[c]);
+      if constexpr (MODE == R_GRADW) t2 += vv * static_cast<Acc>(a.v2[c]);
+    }
+    t = group_sum<LPR>(t);
+    if constexpr (MODE == R_GRADW) t2 = group_sum<LPR>(t2);
+    if (lane != 0) continue;
+    const double td = static_cast<double>(t);
+    if (row < a.p_rows) {
+      if constexpr (MODE == R_MATVEC || MODE == R_RESID || MODE == R_PU) {
+        a.u[row] = a.w[row] * td;
+      } else if constexpr (MODE == R_GRADW) {
+        const double dv = a.d ? a.d[row] : 0.0;
+        a.gw[row] = -td * (static_cast<double>(t2) - dv);
+      }
+      continue;
+    }
+    const int i = row - a.p_rows;
+    const bool hl = has_lo(a.lA[i]), hu = has_hi(a.uA[i]);
+    if constexpr (MODE == R_MATVEC) {
+      const double vlo = a.vl[me + i], vup = a.vl[me + m + i];
+      const double dlo = a.dl[me + i], dup = a.dl[me + m + i];
+      const double ylo = (hl ? td : 0.0) + dlo * vlo;
+      const double yup = (hu ? -td : 0.0) + dup * vup;
+      a.yl[me + i] = ylo;
+      a.yl[me + m + i] = yup;
+      a.wA[i] = (hl ? 2.0 * td / dlo + vlo : 0.0) - (hu ? -2.0 * td / dup + vup : 0.0);
+      acc0 += vlo * ylo + vup * yup;
+    } else if constexpr (MODE == R_RESID) {
+      const ResOff o(n, m, me);
+      const double ll = a.lam[me + i], lu = a.lam[me + m + i];
+      const double sl = a.s[i], su = a.s[m + i];
+      const double rl = hl ? td - sl - a.lA[i] : 0.0;
+      const double ru = hu ? -td - su + a.uA[i] : 0.0;
+      const double c1 = hl ? ll * sl - a.mu : 0.0;
+      const double c2 = hu ? lu * su - a.mu : 0.0;
+      a.resw[o.rlA + i] = rl;
+      a.resw[o.ruA + i] = ru;
+      a.resw[o.rc1 + i] = c1;
+      a.resw[o.rc2 + i] = c2;
+      a.wA[i] = (hu ? lu : 0.0) - (hl ? ll : 0.0);
+      acc0 += rl * rl + ru * ru;
+      acc1 += c1 * c1 + c2 * c2;
+    } else if constexpr (MODE == R_RECOVER) {
+      const ResOff o(n, m, me);
+      const double dsl = hl ? td + a.res[o.rlA + i] : 0.0;
+      const double dsu = hu ? -td + a.res[o.ruA + i] : 0.0;
+      a.ds[i] = dsl;
+      a.ds[m + i] = dsu;
+      const double dll = a.dlam[me + i], dlu = a.dlam[me + m + i];
+      if (hl && dsl < 0.0) mn0 = fmin(mn0, -a.s[i] / dsl);
+      if (hu && dsu < 0.0) mn0 = fmin(mn0, -a.s[m + i] / dsu);
+      if (hl && dll < 0.0) mn1 = fmin(mn1, -a.lam[me + i] / dll);
+      if (hu && dlu < 0.0) mn1 = fmin(mn1, -a.lam[me + m + i] / dlu);
+    } else if constexpr (MODE == R_INIT) {
+      a.ds[i] = hl ? fmax(td - a.lA[i], 1.0) : 0.0;          // ds aliases s here
+      a.ds[m + i] = hu ? fmax(a.uA[i] - td, 1.0) : 0.0;
+      a.yl[me + i] = hl ? 1.0 : 0.0;                          // yl aliases lam here
+      a.yl[me + m + i] = hu ? 1.0 : 0.0;
+    }
+  }
+  if constexpr (MODE == R_MATVEC || MODE == R_RESID) {
+    const double s0 = block_sum(acc0);
+    const double s1 = block_sum(acc1);
+    if (threadIdx.x == 0) {
+      a.part0[blockIdx.x] = s0;
+      if (a.part1) a.part1[blockIdx.x] = s1;
+    }
+  } else if constexpr (MODE == R_RECOVER) {
+    const double s0 = block_min(mn0);
+    const double s1 = block_min(mn1);
+    if (threadIdx.x == 0) {
+      a.part0[blockIdx.x] = s0;
+      a.part1[blockIdx.x] = s1;
+    }
+  }
+}
+
+// ---------------------------------------------------- column-side pass
+// One group of LPR lanes per variable j: segments of XS row j, the low-rank
+// row U_j, the equality columns C_:j, then a per-mode epilogue.
+template <int MODE, int VK, int LPR>
+__global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
+  using T = typename VT<VK>::T;
+  using Acc = typename VT<VK>::Acc;
+  if (a.done && *a.done) return;
+  if (a.bump && blockIdx.x == 0 && threadIdx.x == 0) *a.bump += 1;
+  const T* __restrict__ val = static_cast<const T*>(a.val);
+  const T* __restrict__ U = static_cast<const T*>(a.U);
+  const int lane = threadIdx.x & (LPR - 1);
+  const int gid = (blockIdx.x * kBlock + threadIdx.x) / LPR;
+  const int ng = gridDim.x * (kBlock / LPR);
+  const int n = a.n, m = a.m, me = a.me, k = a.k;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  for (int j = gid; j < n; j += ng) {
+    Acc acc = 0, acc2 = 0;
+    if (val) {
+      const int b0 = a.rowptr[j], b1 = a.seg1[j], b2 = a.seg2[j], b3 = a.rowptr[j + 1];
+      if (MODE != X_RHS && MODE != X_DIAGH && MODE != X_CEFF && a.use_hx) {
+        for (int q = b0 + lane; q < b1; q += LPR)
+          acc += ldv(val, q) * static_cast<Acc>(a.src_hx[a.col[q]]);
+      }
+      if (a.use_pt) {
+        for (int q = b1 + lane; q < b2; q += LPR) {
+          const int c = a.col[q];
+          const Acc vv = ldv(val, q);
+          if constexpr (MODE == X_DIAGH) acc += vv * vv * static_cast<Acc>(a.w[c]);
+          else if constexpr (MODE == X_CEFF) acc += vv * static_cast<Acc>(a.w[c] * a.src_pt[c]);
+          else acc += vv * static_cast<Acc>(a.src_pt[c]);
+        }
+      }
+      if (a.use_at) {
+        for (int q = b2 + lane; q < b3; q += LPR) {
+          const int c = a.col[q];
+          const Acc vv = ldv(val, q);
+          acc += vv * static_cast<Acc>(a.src_at[c]);
+          if constexpr (MODE == X_RHS) acc2 += vv * vv * static_cast<Acc>(a.src_at2[c]);
+        }
+      }
+    }
+    if constexpr (MODE == X_MATVEC || MODE == X_RESID || MODE == X_OBJ || MODE == X_DIAGH) {
+      if (k > 0) {
+        const int64_t base = static_cast<int64_t>(j) * k;
+        for (int l = lane; l < k; l += LPR) {
+          const Acc uv = ldv(U, base + l);
+          if constexpr (MODE == X_DIAGH) acc += uv * uv * static_cast<Acc>(a.wd[l]);
+          else acc += uv * static_cast<Acc>(a.g[l]);
+        }
+      }
+    }
+    acc = group_sum<LPR>(acc);
+    if constexpr (MODE == X_RHS) acc2 = group_sum<LPR>(acc2);
+    if (lane != 0) continue;
+    double y = static_cast<double>(acc);
+    if constexpr (MODE == X_MATVEC) {
+      for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + j] * a.we[e];
+      const double vj = a.v[j];
+      y += a.qdiag[j] * vj;
+      a.y[j] = y;
+      p0 += vj * y;
+    } else if constexpr (MODE == X_RESID) {
+      const ResOff o(n, m, me);
+      const double xj = a.v[j];
+      for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + j] * a.we[e];
+      if (a.h0) y += a.h0[j] * xj;
+      y += a.c[j];
+      const bool hl = has_lo(a.lx[j]), hu = has_hi(a.ux[j]);
+      const double llx = hl ? a.lam[me + 2 * m + j] : 0.0;
+      const double lux = hu ? a.lam[me + 2 * m + n + j] : 0.0;
+      const double slx = a.s[2 * m + j], sux = a.s[2 * m + n + j];
+      y += -llx + lux;
+      const double rlx = hl ? xj - slx - a.lx[j] : 0.0;
+      const double rux = hu ? -xj - sux + a.ux[j] : 0.0;
+      const double c3 = hl ? llx * slx - a.mu : 0.0;
+      const double c4 = hu ? lux * sux - a.mu : 0.0;
+      a.res[o.rH + j] = y;
+      a.res[o.rlx + j] = rlx;
+      a.res[o.rux + j] = rux;
+      a.res[o.rc3 + j] = c3;
+      a.res[o.rc4 + j] = c4;
+      p0 += y * y;
+      p1 += rlx * rlx + rux * rux;
+      p2 += c3 * c3 + c4 * c4;
+    } else if constexpr (MODE == X_RHS) {
+      const ResOff o(n, m, me);
+      const bool hl = has_lo(a.lx[j]), hu = has_hi(a.ux[j]);
+      const double llx = hl ? a.lam[me + 2 * m + j] : 0.0;
+      const double lux = hu ? a.lam[me + 2 * m + n + j] : 0.0;
+      const double slx = hl ? a.s[2 * m + j] : 1.0, sux = hu ? a.s[2 * m + n + j] : 1.0;
+      const double rH = a.res_in[o.rH + j];
+      const double rlx = a.res_in[o.rlx + j], rux = a.res_in[o.rux + j];
+      const double c3 = a.res_in[o.rc3 + j], c4 = a.res_in[o.rc4 + j];
+      const double qb = (hl ? llx / slx : 0.0) + (hu ? lux / sux : 0.0);
+      double r1 = -rH;
+      if (hl) r1 += -c3 / slx - llx / slx * rlx;
+      if (hu) r1 += c4 / sux + lux / sux * rux;
+      double top = r1 + y;
+      double jd = a.diagH[j] + qb + static_cast<double>(acc2);
+      for (int e = 0; e < me; ++e) {
+        const double cej = a.Cm[static_cast<int64_t>(e) * n + j];
+        top += cej * a.we[e];
+        jd += 2.0 * cej * cej / a.mu;
+      }
+      a.rhs[j] = top;
+      a.jdiag[j] = jd;
+      a.qdiag_out[j] = (a.h0 ? a.h0[j] : 0.0) + qb;
+    } else if constexpr (MODE == X_DIAGH) {
+      a.y[j] = a.v[j] + y;
+    } else if constexpr (MODE == X_CEFF) {
+      a.y[j] = a.c[j] - y;
+    } else if constexpr (MODE == X_OBJ) {
+      const double xj = a.v[j];
+      if (a.h0) y += a.h0[j] * xj;
+      p0 += xj * (0.5 * y + a.c[j]);
+    }
+  }
+  if constexpr (MODE == X_MATVEC || MODE == X_RESID || MODE == X_OBJ) {
+    const double s0 = block_sum(p0);
+    double s1 = 0.0, s2 = 0.0;
+    if constexpr (MODE == X_RESID) {
+      s1 = block_sum(p1);
+      s2 = block_sum(p2);
+    }
+    if (threadIdx.x == 0) {
+      a.part0[blockIdx.x] = s0;
+      if constexpr (MODE == X_RESID) {
+        a.part1[blockIdx.x] = s1;
+        a.part2[blockIdx.x] = s2;
+      }
+    }
+  }
+}
+
+// ------------------------------------------ tall-skinny dense reduction
+// Block b reduces rows [b*chunk, (b+1)*chunk) of U (n x k, row-major) into
+// part[b][0..k) and of C (me x n) into part[b][k..k+me).  Each wave owns a
+// 64-column tile and every fourth row, so a wave reads 64 consecutive values
+// of a row per step.
+template <int VK>
+__global__ __launch_bounds__(kBlock) void k_ts_reduce(TsArgs a) {
+  using T = typename VT<VK>::T;
+  using Acc = typename VT<VK>::Acc;
+  if (a.done && *a.done) return;
+  __shared__ double red[kBlock];
+  const T* __restrict__ U = static_cast<const T*>(a.U);
+  const int KW = a.k + a.me;
+  const int j0 = blockIdx.x * a.chunk;
+  const int j1 = min(a.n, j0 + a.chunk);
+  double* out = a.part + static_cast<int64_t>(blockIdx.x) * KW;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c0 = 0; c0 < a.k; c0 += 64) {
+    const int c = c0 + lane;
+    Acc acc = 0;
+    if (c < a.k) {
+      for (int j = j0 + wv; j < j1; j += kBlock / 64)
+        acc += ldv(U, static_cast<int64_t>(j) * a.k + c) * static_cast<Acc>(a.v[j]);
+    }
+    red[threadIdx.x] = static_cast<double>(acc);
+    __syncthreads();
+    if (wv == 0 && c < a.k) {
+      double s = red[lane];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) s += red[w * 64 + lane];
+      out[c] = s;
+    }
+    __syncthreads();
+  }
+  for (int e = 0; e < a.me; ++e) {
+    double acc = 0.0;
+    for (int j = j0 + threadIdx.x; j < j1; j += kBlock)
+      acc += a.Cm[static_cast<int64_t>(e) * a.n + j] * a.v[j];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[a.k + e] = acc;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_ts_finish(TsFinishArgs a) {
+  if (a.done && *a.done) return;
+  const int KW = a.k + a.me;
+  for (int l = threadIdx.x; l < KW; l += kBlock) {
+    double s = 0.0;
+    for (int b = 0; b < a.grid; ++b) s += a.part[static_cast<int64_t>(b) * KW + l];
+    if (l < a.k) a.g[l] = a.wd[l] * s;
+    else a.te[l - a.k] = s;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if constexpr (MODE == TS_MATVEC) {
+    for (int e = threadIdx.x; e < a.me; e += kBlock) {
+      const double te = a.te[e], ve = a.vl[e];
+      a.we[e] = 2.0 * te / a.mu + ve;
+      const double ye = te + a.mu * ve;
+      a.yl[e] = ye;
+      acc += ve * ye;
+    }
+  } else if constexpr (MODE == TS_RESID) {
+    for (int e = threadIdx.x; e < a.me; e += kBlock) {
+      const double re = a.te[e] - a.b[e] + a.mu * a.lam[e];
+      a.res[a.n + e] = re;
+      a.we[e] = -a.lam[e];
+      acc += re * re;
+    }
+  }
+  if constexpr (MODE == TS_MATVEC || MODE == TS_RESID) {
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) a.partout[0] = acc;
+  }
+}
+
+// ------------------------------------------------------ IPM step kernels
+// Right-hand side rows of the lam-part and the D blocks (eq. (8)/(9)):
+//   D = (mu, s_lA/lam_lA, s_uA/lam_uA),  r2 = (-r_e, -r_lA - r_c1/lam_lA, -r_uA - r_c2/lam_uA)
+// plus the per-row weights of 2 B^T D^-1 r2 (wA) and of diag(2 B^T D^-1 B) (jw).
+__global__ __launch_bounds__(kBlock) void k_rhs_lam(VecArgs a) {
+  const int n = a.n, m = a.m, me = a.me;
+  const ResOff o(n, m, me);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < me + m; i += gridDim.x * kBlock) {
+    if (i < me) {
+      const double r2 = -a.res[o.re + i];
+      a.rhs[n + i] = r2;
+      a.jdiag[n + i] = a.mu;
+      a.dl[i] = a.mu;
+      a.we[i] = 2.0 * r2 / a.mu;
+      continue;
+    }
+    const int r = i - me;
+    const bool hl = has_lo(a.lA[r]), hu = has_hi(a.uA[r]);
+    const double ll = a.lam[me + r], lu = a.lam[me + m + r];
+    const double dL = hl ? a.s[r] / ll : 1.0;
+    const double dU = hu ? a.s[m + r] / lu : 1.0;
+    const double r2L = hl ? -a.res[o.rlA + r] - a.res[o.rc1 + r] / ll : 0.0;
+    const double r2U = hu ? -a.res[o.ruA + r] - a.res[o.rc2 + r] / lu : 0.0;
+    a.rhs[n + me + r] = r2L;
+    a.rhs[n + me + m + r] = r2U;
+    a.jdiag[n + me + r] = dL;
+    a.jdiag[n + me + m + r] = dU;
+    a.dl[me + r] = dL;
+    a.dl[me + m + r] = dU;
+    a.wA[r] = (hl ? 2.0 * r2L / dL : 0.0) - (hu ? 2.0 * r2U / dU : 0.0);
+    a.jw[r] = (hl ? 2.0 / dL : 0.0) + (hu ? 2.0 / dU : 0.0);
+  }
+}
+
+// Variable-bound part of the recovery (complementarity rows of eq. (7)) and
+// of the ratio test (eq. (10)).
+__global__ __launch_bounds__(kBlock) void k_recover_x(VecArgs a) {
+  const int n = a.n, m = a.m, me = a.me;
+  const ResOff o(n, m, me);
+  double ms = INFINITY, ml = INFINITY;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
+    const bool hl = has_lo(a.lx[j]), hu = has_hi(a.ux[j]);
+    const double dxj = a.dx[j];
+    double dsl = 0.0, dsu = 0.0, dll = 0.0, dlu = 0.0;
+    if (hl) {
+      const double slx = a.s[2 * m + j], llx = a.lam[me + 2 * m + j];
+      dsl = dxj + a.res[o.rlx + j];
+      dll = -(a.res[o.rc3 + j] + llx * dsl) / slx;
+      if (dsl < 0.0) ms = fmin(ms, -slx / dsl);
+      if (dll < 0.0) ml = fmin(ml, -llx / dll);
+    }
+    if (hu) {
+      const double sux = a.s[2 * m + n + j], lux = a.lam[me + 2 * m + n + j];
+      dsu = -dxj + a.res[o.rux + j];
+      dlu = -(a.res[o.rc4 + j] + lux * dsu) / sux;
+      if (dsu < 0.0) ms = fmin(ms, -sux / dsu);
+      if (dlu < 0.0) ml = fmin(ml, -lux / dlu);
+    }
+    a.ds[2 * m + j] = dsl;
+    a.ds[2 * m + n + j] = dsu;
+    a.dlam_w[me + 2 * m + j] = dll;
+    a.dlam_w[me + 2 * m + n + j] = dlu;
+  }
+  ms = block_min(ms);
+  ml = block_min(ml);
+  if (threadIdx.x == 0) {
+    a.part[P_MIN_S_X * kGridMax + blockIdx.x] = ms;
+    a.part[P_MIN_L_X * kGridMax + blockIdx.x] = ml;
+  }
+}
+
+// alpha = min(1, gamma * min ratio); an empty set gives 1 (eq. (10)).
+__global__ __launch_bounds__(kBlock) void k_finish_ratio(VecArgs a, int g_r, int g_x) {
+  const double* P = a.part;
+  const double ms = fmin(min_bcast(P + P_MIN_S_R * kGridMax, g_r), min_bcast(P + P_MIN_S_X * kGridMax, g_x));
+  const double ml = fmin(min_bcast(P + P_MIN_L_R * kGridMax, g_r), min_bcast(P + P_MIN_L_X * kGridMax, g_x));
+  if (threadIdx.x == 0) {
+    a.sc[S_ALPHA_X] = fmin(1.0, a.gamma * ms);
+    a.sc[S_ALPHA_L] = fmin(1.0, a.gamma * ml);
+  }
+}
+
+// Stacked residual norm and the three infeasibilities of Section 5.2.
+__global__ __launch_bounds__(kBlock) void k_finish_norms(VecArgs a, int g_r, int g_x) {
+  const double* P = a.part;
+  const double pr = sum_bcast(P + P_NR_PRIMAL * kGridMax, g_r) + sum_bcast(P + P_NX_PRIMAL * kGridMax, g_x);
+  const double du = sum_bcast(P + P_NX_DUAL * kGridMax, g_x);
+  const double co = sum_bcast(P + P_NR_COMPL * kGridMax, g_r) + sum_bcast(P + P_NX_COMPL * kGridMax, g_x);
+  const double re = P[P_NTS_RE * kGridMax];
+  if (threadIdx.x == 0) {
+    a.sc[S_NORM] = sqrt(pr + du + co + re);
+    a.sc[S_PRIMAL] = sqrt(pr);
+    a.sc[S_DUAL] = sqrt(du);
+    a.sc[S_COMPL] = sqrt(co);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_sum(const double* part, int count, double* out) {
+  const double s = sum_bcast(part, count);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// x += ax dx, s += ax ds, lam += al dlam over present entries (Algorithm 1).
+__global__ __launch_bounds__(kBlock) void k_update(VecArgs a, const double* dx, const double* dlam,
+                                                  const double* ds, const double* alpha_dev,
+                                                  double ax, double al) {
+  const int n = a.n, m = a.m, me = a.me;
+  if (alpha_dev) {
+    ax = alpha_dev[0];
+    al = alpha_dev[1];
+  }
+  const int total = me + 2 * m + 2 * n;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    if (i < n) a.x[i] += ax * dx[i];
+    bool present;
+    if (i < me) {
+      a.lam[i] += al * dlam[i];
+    } else {
+      const int q = i - me;  // index into the s layout
+      if (q < m) present = has_lo(a.lA[q]);
+      else if (q < 2 * m) present = has_hi(a.uA[q - m]);
+      else if (q < 2 * m + n) present = has_lo(a.lx[q - 2 * m]);
+      else present = has_hi(a.ux[q - 2 * m - n]);
+      if (present) {
+        a.lam[i] += al * dlam[i];
+        a.s[q] += ax * ds[q];
+      }
+    }
+  }
+}
+
+// Default starting point, variable part (the row slacks follow in R_INIT).
+__global__ __launch_bounds__(kBlock) void k_init_x(VecArgs a) {
+  const int n = a.n, m = a.m, me = a.me;
+  const int total = n > me ? n : me;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < total; j += gridDim.x * kBlock) {
+    if (j < me) a.lam[j] = 0.0;
+    if (j >= n) continue;
+    const double l = a.lx[j], u = a.ux[j];
+    const bool hl = has_lo(l), hu = has_hi(u);
+    double x = 0.0;
+    if (hl && hu) x = 0.5 * (l + u);
+    else if (hl) x = l + 1.0;
+    else if (hu) x = u - 1.0;
+    a.x[j] = x;
+    a.s[2 * m + j] = hl ? x - l : 0.0;
+    a.s[2 * m + n + j] = hu ? u - x : 0.0;
+    a.lam[me + 2 * m + j] = hl ? 1.0 : 0.0;
+    a.lam[me + 2 * m + n + j] = hu ? 1.0 : 0.0;
+  }
+}
+
+// Validates a caller iterate: counts present entries that are not finite and
+// positive, and zeroes the entries of absent sides.
+__global__ __launch_bounds__(kBlock) void k_check_state(VecArgs a) {
+  const int n = a.n, m = a.m, me = a.me;
+  const int total = me + 2 * m + 2 * n;
+  double bad = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    if (i < n && !isfinite(a.x[i])) bad += 1.0;
+    if (i < me) {
+      if (!isfinite(a.lam[i])) bad += 1.0;
+      continue;
+    }
+    const int q = i - me;
+    bool present;
+    if (q < m) present = has_lo(a.lA[q]);
+    else if (q < 2 * m) present = has_hi(a.uA[q - m]);
+    else if (q < 2 * m + n) present = has_lo(a.lx[q - 2 * m]);
+    else present = has_hi(a.ux[q - 2 * m - n]);
+    if (present) {
+      const double l = a.lam[i], s = a.s[q];
+      if (!(isfinite(l) && l > 0.0 && isfinite(s) && s > 0.0)) bad += 1.0;
+    } else {
+      a.lam[i] = 0.0;
+      a.s[q] = 0.0;
+    }
+  }
+  bad = block_sum(bad);
+  if (threadIdx.x == 0) a.part[P_CHK * kGridMax + blockIdx.x] = bad;
+}
+
+// ------------------------------------------------------------ PCG kernels
+// Textbook Jacobi PCG on eq. (9) (Sections 3.1, 5.1): x0 = 0, z = r / diag,
+// stop when ||r||_2 <= tol ||rhs||_2 or at maxit.  Scalars are never stored by
+// one block for the others: every block re-sums the partials it needs, so the
+// only cross-block state is the partial arrays and the flags.  rz partials
+// alternate between two regions by iteration parity.
+__global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
+  double rz = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock) {
+    const double r = a.rhs[i];
+    const double z = r / a.jdiag[i];
+    a.x[i] = 0.0;
+    a.r[i] = r;
+    a.z[i] = z;
+    a.p[i] = z;
+    rz += r * z;
+    rr += r * r;
+  }
+  rz = block_sum(rz);
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) {
+    a.part[P_RZ0 * kGridMax + blockIdx.x] = rz;
+    a.part[P_RR0 * kGridMax + blockIdx.x] = rr;
+    if (blockIdx.x == 0) {
+      a.fl[F_DONE] = 0;
+      a.fl[F_CNT] = -1;
+      a.fl[F_STATUS] = 0;
+      a.fl[F_ITERS] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgArgs a) {
+  const double rr0 = sum_bcast(a.part + P_RR0 * kGridMax, a.g_vec);
+  if (threadIdx.x == 0) {
+    a.sc[S_RHSNORM] = sqrt(rr0);
+    if (!(rr0 > 0.0)) {
+      a.fl[F_DONE] = 1;
+      a.fl[F_STATUS] = (rr0 == 0.0) ? 1 : QP_ERR_NUMERIC_CODE;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
+  if (a.fl[F_DONE]) return;
+  const int k = a.fl[F_CNT];
+  const double* P = a.part;
+  double pq = sum_bcast(P + P_DOT_R * kGridMax, a.g_r) + sum_bcast(P + P_DOT_X * kGridMax, a.g_x);
+  if (a.has_ts) pq += P[P_DOT_TS * kGridMax];
+  const double rz = sum_bcast(P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec);
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.fl[F_STATUS] = (isfinite(pq) && isfinite(rz)) ? QP_ERR_NOT_SPD_CODE : QP_ERR_NUMERIC_CODE;
+      a.fl[F_ITERS] = k;
+      a.fl[F_DONE] = 1;
+    }
+    return;
+  }
+  const double alpha = rz / pq;
+  double rzn = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock) {
+    a.x[i] += alpha * a.p[i];
+    const double r = a.r[i] - alpha * a.q[i];
+    const double z = r / a.jdiag[i];
+    a.r[i] = r;
+    a.z[i] = z;
+    rzn += r * z;
+    rr += r * r;
+  }
+  rzn = block_sum(rzn);
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) {
+    a.part[(((k + 1) & 1) ? P_RZ1 : P_RZ0) * kGridMax + blockIdx.x] = rzn;
+    a.part[P_RR * kGridMax + blockIdx.x] = rr;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(CgArgs a) {
+  if (a.fl[F_DONE]) return;
+  const int k = a.fl[F_CNT];
+  const double* P = a.part;
+  const double rz_old = sum_bcast(P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec);
+  const double rz_new = sum_bcast(P + (((k + 1) & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec);
+  const double rr = sum_bcast(P + P_RR * kGridMax, a.g_vec);
+  const bool conv = sqrt(rr) <= a.tol * a.sc[S_RHSNORM];
+  if (conv || k + 1 >= a.maxit) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.fl[F_ITERS] = k + 1;
+      a.fl[F_STATUS] = conv ? 1 : 2;
+      a.fl[F_DONE] = 1;
+    }
+    return;
+  }
+  const double beta = rz_new / rz_old;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock)
+    a.p[i] = a.z[i] + beta * a.p[i];
+}
+
+// Residual replacement for the reduced-precision operator: r = rhs - K x with
+// the float64 operator, then restart the recurrence from z = r / diag.
+__global__ __launch_bounds__(kBlock) void k_cg_restart(CgArgs a, const double* kx) {
+  if (a.fl[F_DONE]) return;
+  const int k = a.fl[F_CNT] + 1;  // the iteration about to run
+  double rz = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock) {
+    const double r = a.rhs[i] - kx[i];
+    const double z = r / a.jdiag[i];
+    a.r[i] = r;
+    a.z[i] = z;
+    a.p[i] = z;
+    rz += r * z;
+  }
+  rz = block_sum(rz);
+  if (threadIdx.x == 0) a.part[((k & 1) ? P_RZ1 : P_RZ0) * kGridMax + blockIdx.x] = rz;
+}
+
+// Squared distance partials (true residual ||rhs - K x||^2).
+__global__ __launch_bounds__(kBlock) void k_sqdiff(const double* a, const double* b, int64_t n,
+                                                  double* part) {
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const double d = a[i] - b[i];
+    acc += d * d;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Ratio test of eq. (10) for a caller-given direction (iterate layouts).
+__global__ __launch_bounds__(kBlock) void k_ratio_given(VecArgs a, const double* dlam, const double* ds) {
+  const int n = a.n, m = a.m, me = a.me;
+  double ms = INFINITY, ml = INFINITY;
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < 2 * m + 2 * n; q += gridDim.x * kBlock) {
+    bool present;
+    if (q < m) present = has_lo(a.lA[q]);
+    else if (q < 2 * m) present = has_hi(a.uA[q - m]);
+    else if (q < 2 * m + n) present = has_lo(a.lx[q - 2 * m]);
+    else present = has_hi(a.ux[q - 2 * m - n]);
+    if (!present) continue;
+    const double dsq = ds[q], dlq = dlam[me + q];
+    if (dsq < 0.0) ms = fmin(ms, -a.s[q] / dsq);
+    if (dlq < 0.0) ml = fmin(ml, -a.lam[me + q] / dlq);
+  }
+  ms = block_min(ms);
+  ml = block_min(ml);
+  if (threadIdx.x == 0) {
+    a.part[P_MIN_S_X * kGridMax + blockIdx.x] = ms;
+    a.part[P_MIN_L_X * kGridMax + blockIdx.x] = ml;
+  }
+}
+
+// ------------------------------------------------------------- backward
+__global__ __launch_bounds__(kBlock) void k_grad_out(int n, int m, int me, const double* u,
+                                                    const double* lA, const double* uA,
+                                                    double* gc, double* glA, double* guA,
+                                                    double* gb) {
+  const int total = n > m ? n : m;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    if (gc && i < n) gc[i] = -u[i];
+    if (i < m) {
+      if (glA) glA[i] = has_lo(lA[i]) ? -u[n + me + i] : 0.0;
+      if (guA) guA[i] = has_hi(uA[i]) ? u[n + me + m + i] : 0.0;
+    }
+    if (gb && i < me) gb[i] = -u[n + i];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const double* src, double* dst, int64_t n, double scale) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    dst[i] = scale * src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double* dst, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    dst[i] = v;
+}
+
+// ------------------------------------------------------------- launchers
+static inline int grid_for(int64_t items, int per_block) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > kGridMax) g = kGridMax;
+  return static_cast<int>(g);
+}
+
+template <int MODE, int VK>
+static hipError_t rowpass_lpr(int lpr, const RowArgs& a, int grid, hipStream_t st) {
+  switch (lpr) {
+    case 4: k_rowpass<MODE, VK, 4><<<grid, kBlock, 0, st>>>(a); break;
+    case 8: k_rowpass<MODE, VK, 8><<<grid, kBlock, 0, st>>>(a); break;
+    case 16: k_rowpass<MODE, VK, 16><<<grid, kBlock, 0, st>>>(a); break;
+    case 32: k_rowpass<MODE, VK, 32><<<grid, kBlock, 0, st>>>(a); break;
+    default: k_rowpass<MODE, VK, 64><<<grid, kBlock, 0, st>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE, int VK>
+static hipError_t colpass_lpr(int lpr, const ColArgs& a, int grid, hipStream_t st) {
+  switch (lpr) {
+    case 4: k_colpass<MODE, VK, 4><<<grid, kBlock, 0, st>>>(a); break;
+    case 8: k_colpass<MODE, VK, 8><<<grid, kBlock, 0, st>>>(a); break;
+    case 16: k_colpass<MODE, VK, 16><<<grid, kBlock, 0, st>>>(a); break;
+    case 32: k_colpass<MODE, VK, 32><<<grid, kBlock, 0, st>>>(a); break;
+    default: k_colpass<MODE, VK, 64><<<grid, kBlock, 0, st>>>(a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid, hipStream_t st) {
+  if (mode == R_MATVEC) {
+    if (vk == VK_F32) return rowpass_lpr<R_MATVEC, VK_F32>(lpr, a, grid, st);
+    if (vk == VK_BF16) return rowpass_lpr<R_MATVEC, VK_BF16>(lpr, a, grid, st);
+    return rowpass_lpr<R_MATVEC, VK_F64>(lpr, a, grid, st);
+  }
+  switch (mode) {
+    case R_RESID: return rowpass_lpr<R_RESID, VK_F64>(lpr, a, grid, st);
+    case R_RECOVER: return rowpass_lpr<R_RECOVER, VK_F64>(lpr, a, grid, st);
+    case R_GRADW: return rowpass_lpr<R_GRADW, VK_F64>(lpr, a, grid, st);
+    case R_PU: return rowpass_lpr<R_PU, VK_F64>(lpr, a, grid, st);
+    case R_INIT: return rowpass_lpr<R_INIT, VK_F64>(lpr, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid, hipStream_t st) {
+  if (mode == X_MATVEC) {
+    if (vk == VK_F32) return colpass_lpr<X_MATVEC, VK_F32>(lpr, a, grid, st);
+    if (vk == VK_BF16) return colpass_lpr<X_MATVEC, VK_BF16>(lpr, a, grid, st);
+    return colpass_lpr<X_MATVEC, VK_F64>(lpr, a, grid, st);
+  }
+  switch (mode) {
+    case X_RESID: return colpass_lpr<X_RESID, VK_F64>(lpr, a, grid, st);
+    case X_RHS: return colpass_lpr<X_RHS, VK_F64>(lpr, a, grid, st);
+    case X_DIAGH: return colpass_lpr<X_DIAGH, VK_F64>(lpr, a, grid, st);
+    case X_CEFF: return colpass_lpr<X_CEFF, VK_F64>(lpr, a, grid, st);
+    case X_OBJ: return colpass_lpr<X_OBJ, VK_F64>(lpr, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st) {
+  if (vk == VK_F32) k_ts_reduce<VK_F32><<<grid, kBlock, 0, st>>>(a);
+  else if (vk == VK_BF16) k_ts_reduce<VK_BF16><<<grid, kBlock, 0, st>>>(a);
+  else k_ts_reduce<VK_F64><<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ts_finish(int mode, const TsFinishArgs& a, hipStream_t st) {
+  if (mode == TS_MATVEC) k_ts_finish<TS_MATVEC><<<1, kBlock, 0, st>>>(a);
+  else if (mode == TS_RESID) k_ts_finish<TS_RESID><<<1, kBlock, 0, st>>>(a);
+  else k_ts_finish<TS_GONLY><<<1, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_lam(const VecArgs& a, hipStream_t st) {
+  if (a.me + a.m == 0) return hipSuccess;
+  k_rhs_lam<<<grid_for(a.me + a.m, kBlock), kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_recover_x(const VecArgs& a, int grid, hipStream_t st) {
+  k_recover_x<<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_finish_ratio(const VecArgs& a, int g_r, int g_x, hipStream_t st) {
+  k_finish_ratio<<<1, kBlock, 0, st>>>(a, g_r, g_x);
+  return hipGetLastError();
+}
+hipError_t launch_finish_norms(const VecArgs& a, int g_r, int g_x, hipStream_t st) {
+  k_finish_norms<<<1, kBlock, 0, st>>>(a, g_r, g_x);
+  return hipGetLastError();
+}
+hipError_t launch_update(const VecArgs& a, const double* dx, const double* dlam, const double* ds,
+                         const double* alpha_dev, double ax, double al, int grid, hipStream_t st) {
+  k_update<<<grid, kBlock, 0, st>>>(a, dx, dlam, ds, alpha_dev, ax, al);
+  return hipGetLastError();
+}
+hipError_t launch_init_x(const VecArgs& a, int grid, hipStream_t st) {
+  k_init_x<<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_check_state(const VecArgs& a, int grid, hipStream_t st) {
+  k_check_state<<<grid, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_finish_sum(const double* part, int count, double* out, hipStream_t st) {
+  k_finish_sum<<<1, kBlock, 0, st>>>(part, count, out);
+  return hipGetLastError();
+}
+hipError_t launch_cg_init(const CgArgs& a, hipStream_t st) {
+  k_cg_init<<<a.g_vec, kBlock, 0, st>>>(a);
+  k_cg_init_finish<<<1, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update(const CgArgs& a, hipStream_t st) {
+  k_cg_update<<<a.g_vec, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st) {
+  k_cg_pupdate<<<a.g_vec, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+hipError_t launch_cg_restart(const CgArgs& a, const double* kx, hipStream_t st) {
+  k_cg_restart<<<a.g_vec, kBlock, 0, st>>>(a, kx);
+  return hipGetLastError();
+}
+hipError_t launch_grad_out(int n, int m, int me, const double* u, const double* lA,
+                           const double* uA, double* gc, double* glA, double* guA, double* gb,
+                           hipStream_t st) {
+  k_grad_out<<<grid_for(n > m ? n : m, kBlock), kBlock, 0, st>>>(n, m, me, u, lA, uA, gc, glA, guA, gb);
+  return hipGetLastError();
+}
+hipError_t launch_copy(const double* src, double* dst, int64_t n, double scale, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_copy<<<grid_for(n, kBlock), kBlock, 0, st>>>(src, dst, n, scale);
+  return hipGetLastError();
+}
+hipError_t launch_sqdiff(const double* a, const double* b, int64_t n, double* part, int grid,
+                         hipStream_t st) {
+  k_sqdiff<<<grid, kBlock, 0, st>>>(a, b, n, part);
+  return hipGetLastError();
+}
+hipError_t launch_ratio_given(const VecArgs& a, const double* dlam, const double* ds, int grid,
+                              hipStream_t st) {
+  k_ratio_given<<<grid, kBlock, 0, st>>>(a, dlam, ds);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill<<<grid_for(n, kBlock), kBlock, 0, st>>>(dst, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace qpk

@@ -70,3 +70,27 @@ def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def res_to_masked(prob, res):
+    """Oracle residual blocks -> the library's residual stack
+    [rH n | re me | rlA m | ruA m | rlx n | rux n | rc1 m | rc2 m | rc3 n | rc4 n]."""
+    S = O.index_sets(prob)
+    n, m, me = prob.n, prob.m, prob.me
+    out = []
+    out.append(res.rH)
+    out.append(res.re)
+    for idx, blk, size in ((S.L, res.rlA, m), (S.U, res.ruA, m), (S.Lx, res.rlx, n),
+                           (S.Ux, res.rux, n), (S.L, res.rc1, m), (S.U, res.rc2, m),
+                           (S.Lx, res.rc3, n), (S.Ux, res.rc4, n)):
+        v = np.zeros(size)
+        v[idx] = blk
+        out.append(v)
+    return np.concatenate(out)
+
+
+def dir_to_masked(prob, d):
+    """Oracle Direction -> (dx, dlam, ds) in the library's iterate layouts."""
+    st = O.State(d.dx, d.dlam_e, d.dlam_lA, d.dlam_uA, d.dlam_lx, d.dlam_ux,
+                 d.ds_lA, d.ds_uA, d.ds_lx, d.ds_ux)
+    return to_masked(prob, st)

@@ -1,0 +1,162 @@
+"""GPU parity of every step of the hot path against the CPU oracle, through
+the C ABI (steps a1-a8 at arbitrary interior states, then Algorithm 1)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import (dir_to_masked, from_masked, kkt_from_masked, kkt_to_masked,
+                           random_state, rel, res_to_masked, to_masked)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _cases():
+    return {
+        "general_dense": lambda: W.random_bounded_qp(1, 37, 29, 2, 11),
+        "general_csr_lowrank": lambda: W.random_bounded_qp(2, 53, 41, 1, 9, a_sparse=True,
+                                                           h_kind="lowrank"),
+        "rt_ptwp": lambda: W.rt_qp(5, 700, 61, 0.08, 23, maxdose=0.6),
+        "svm_lowrank_eq": lambda: W.svm_qp(6, 333, 7),
+        "tiny_dense": lambda: W.tiny_dense(0),
+        "no_rows_bounds_only": lambda: W.QPSpec(n=70, c=np.linspace(-3, 3, 70), h_kind="dense",
+                                                H=np.diag(np.linspace(0.5, 2, 70)),
+                                                lx=-np.ones(70), ux=np.ones(70)),
+    }
+
+
+CASES = _cases()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def setup(request):
+    from paper_2308_00637_amd.qpk import QP
+    spec = CASES[request.param]()
+    prob = O.from_spec(spec)
+    qp = QP(spec)
+    rng = np.random.default_rng(42)
+    st = random_state(prob, rng, 0.5)
+    mu = 0.37
+    x, lam, s = to_masked(prob, st)
+    qp.set_state(dev(x), dev(lam), dev(s), mu)
+    print(f"case={request.param} n={prob.n} m={prob.m} me={prob.me}", flush=True)
+    return request.param, spec, prob, qp, st, mu
+
+
+def test_a1_residuals(setup):
+    name, spec, prob, qp, st, mu = setup
+    r, norms = qp.residuals()
+    res = O.residuals(prob, st, mu)
+    ref = res_to_masked(prob, res)
+    assert rel(host(r), ref) <= 1e-12
+    pr, du, co = O.infeasibilities(res)
+    assert norms[0] == pytest.approx(O.stacked_norm(res), rel=1e-12)
+    assert norms[1:] == pytest.approx([pr, du, co], rel=1e-12, abs=1e-300)
+
+
+def test_a2_a3_rhs_and_jacobi(setup):
+    name, spec, prob, qp, st, mu = setup
+    rhs, dg = qp.newton_rhs()
+    ref_rhs, _ = O.newton_rhs_doubly(prob, st, mu)
+    ref_dg = O.jacobi_diagonal(prob, st, mu)
+    assert rel(kkt_from_masked(prob, host(rhs)), ref_rhs) <= 1e-12
+    assert rel(kkt_from_masked(prob, host(dg)), ref_dg) <= 1e-12
+
+
+def test_a4_matvec(setup):
+    name, spec, prob, qp, st, mu = setup
+    rng = np.random.default_rng(7)
+    N = prob.n + prob.me + O.index_sets(prob).L.size + O.index_sets(prob).U.size
+    for _ in range(3):
+        v = rng.standard_normal(N)
+        y = qp.kkt_matvec(dev(kkt_to_masked(prob, v)))
+        ref = O.kkt_matvec(prob, st, mu, v)
+        yh = host(y)
+        assert rel(kkt_from_masked(prob, yh), ref) <= 1e-12
+        # rows of absent sides are identity rows on a zero input
+        assert np.all(yh[np.abs(kkt_to_masked(prob, np.ones(N))) == 0] == 0)
+
+
+def test_a5_pcg_matches_cholesky_and_oracle_pcg(setup):
+    from oracle.pcg import pcg
+    from paper_2308_00637_amd.qpk import default_pcg_options
+    name, spec, prob, qp, st, mu = setup
+    rhs, _ = qp.newton_rhs()
+    ref_rhs, res = O.newton_rhs_doubly(prob, st, mu)
+    Q, B, D, r1, r2, _ = O.reduced_system(prob, st, res, mu)
+    K, _ = O.doubly_augmented(Q, B, D, r1, r2)
+    xd = np.linalg.solve(K, ref_rhs)
+    sol, info = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-12, maxit=20000))
+    assert info.converged == 1 and info.rel_residual <= 1e-11
+    assert rel(kkt_from_masked(prob, host(sol)), xd) <= 1e-7
+    # iteration count at the paper's tolerance agrees with a textbook PCG
+    sol, info = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-7))
+    _, it, conv, _ = pcg(lambda v: K @ v, ref_rhs, np.diag(K), 1e-7, 5000)
+    assert conv and info.converged == 1
+    assert abs(info.iterations - it) <= max(2, it // 50), (info.iterations, it)
+
+
+def test_a6_direction(setup):
+    from paper_2308_00637_amd.qpk import default_pcg_options
+    name, spec, prob, qp, st, mu = setup
+    dx, dl, ds, info = qp.newton_direction(default_pcg_options(tol=1e-13, maxit=20000))
+    d, _, _ = O.newton_direction(prob, st, mu)
+    rx, rl, rs = dir_to_masked(prob, d)
+    assert rel(host(dx), rx) <= 1e-7
+    assert rel(host(dl), rl) <= 1e-7
+    assert rel(host(ds), rs) <= 1e-7
+
+
+def test_a7_a8_step_lengths_and_update(setup):
+    name, spec, prob, qp, st, mu = setup
+    d, _, _ = O.newton_direction(prob, st, mu)
+    rx, rl, rs = dir_to_masked(prob, d)
+    ax, al = qp.step_lengths(dev(rl), dev(rs), 0.99)
+    oax, oal = O.step_lengths(st, d, 0.99)
+    assert ax == pytest.approx(oax, rel=1e-14) and al == pytest.approx(oal, rel=1e-14)
+    x0, l0, s0, _ = qp.get_state()
+    qp.take_step(dev(rx), dev(rl), dev(rs), ax, al)
+    x1, l1, s1, _ = qp.get_state()
+    st1 = O.take_step(st, d, oax, oal)
+    ex, el, es = to_masked(prob, st1)
+    assert rel(host(x1), ex) <= 1e-14 and rel(host(l1), el) <= 1e-14 and rel(host(s1), es) <= 1e-14
+    # restore the module-scoped state
+    qp.set_state(x0, l0, s0, mu)
+
+
+def test_a9_ipm_solve_matches_oracle(setup):
+    name, spec, prob, qp, st, mu = setup
+    ref = O.solve(prob)
+    out = qp.solve(log=True)
+    info = out["info"]
+    assert info.result == 0 and ref.status == "converged"
+    assert abs(info.objective - ref.objective) <= 1e-6 * max(1.0, abs(ref.objective))
+    print(f"ipm iters gpu={info.iterations} oracle={ref.iterations} cg={info.total_cg_iters} "
+          f"cg_cap_hits={info.cg_maxiter_hits} obj={info.objective:.12g}/{ref.objective:.12g}")
+    # KKT residual of the returned point, evaluated by the oracle's own function
+    gst = from_masked(prob, host(out["x"]), host(out["lam"]), host(out["s"]))
+    kkt = O.stacked_norm(O.residuals(prob, gst, info.mu_final))
+    assert kkt <= 1e-6, kkt
+    assert kkt == pytest.approx(info.rnorm, rel=1e-9)
+    # With every PCG solve converged (to 1e-7), the inexact Newton steps stay
+    # close to the exact ones and the mu schedule is the oracle's.  When a
+    # solve stops at the iteration cap its iterate depends on rounding, and the
+    # trajectories may part (the final point is still checked above).
+    if info.cg_maxiter_hits == 0:
+        assert abs(info.iterations - ref.iterations) <= 2, (info.iterations, ref.iterations)
+        assert info.mu_final == pytest.approx(ref.mu, rel=1e-12)
+        ref_mus = [e["mu"] for e in ref.log]
+        k = min(len(ref_mus), info.iterations) - 3
+        assert np.allclose(out["log"]["mu"][:k], ref_mus[:k], rtol=0)
+    else:
+        assert info.mu_final < 1e-6
