@@ -249,6 +249,29 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c,
                       double* grad_lA, double* grad_uA, double* grad_b,
                       double* grad_w, const pcg_options* o, pcg_info* info);
 
+/* Kernel timing with HIP events on the handle's stream (instrumentation, not
+ * part of the method).  qp_profile_begin(h, max_launches) pre-creates events for
+ * up to max_launches timed launches per category; until qp_profile_end every
+ * PCG matvec launch is bracketed by an event pair.  qp_profile_end synchronises
+ * and returns, per category, the number of timed launches and their summed
+ * duration in ms (HOST arrays of QP_PROF_COUNT entries), then frees the
+ * events.  Categories: */
+enum {
+  QP_PROF_ROWPASS = 0,   /* row-side pass of K v (rows of P and A) */
+  QP_PROF_COLPASS = 1,   /* column-side pass of K v (x-part) */
+  QP_PROF_TSREDUCE = 2,  /* dense low-rank reduction U^T v, C v */
+  QP_PROF_CGVEC = 3,     /* the two PCG vector kernels of one iteration, together */
+  QP_PROF_COUNT = 4
+};
+qp_status qp_profile_begin(qp_handle h, int32_t max_launches);
+qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms);
+
+/* Bytes of the stored operators (HOST out): row-side CSR, column-side CSR,
+ * dense low-rank factor, each in the precision the PCG matvec reads, plus
+ * the nonzero counts of the two CSR structures. */
+qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
+                            int64_t* dense_bytes, int64_t* row_nnz, int64_t* col_nnz);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,7 @@ class Problem:
     n: int
     Hmul: Callable[[np.ndarray], np.ndarray]
     Hdense: Callable[[], np.ndarray]
+    Hdiag: Callable[[], np.ndarray]
     p: np.ndarray
     A: object            # dense ndarray or scipy sparse (m x n), may have 0 rows
     l: np.ndarray
@@ -77,6 +78,7 @@ def from_spec(spec) -> Problem:
         Hd = np.array(spec.H, dtype=np.float64)
         Hmul = lambda v: Hd @ v
         Hdense = lambda: Hd
+        Hdiag = lambda: np.diag(Hd).copy()
         p = np.array(spec.c, dtype=np.float64)
     elif spec.h_kind == "lowrank":
         h0 = np.array(spec.h0, dtype=np.float64)
@@ -84,6 +86,7 @@ def from_spec(spec) -> Problem:
         wd = np.array(spec.wd, dtype=np.float64)
         Hmul = lambda v: h0 * v + U @ (wd * (U.T @ v))
         Hdense = lambda: np.diag(h0) + (U * wd) @ U.T
+        Hdiag = lambda: h0 + (U * U) @ wd
         p = np.array(spec.c, dtype=np.float64)
     elif spec.h_kind == "ptwp":
         P = sp.csr_matrix(spec.P, dtype=np.float64)
@@ -91,6 +94,7 @@ def from_spec(spec) -> Problem:
         d = np.array(spec.d, dtype=np.float64)
         Hmul = lambda v: P.T @ (w * (P @ v))
         Hdense = lambda: (P.T @ sp.diags(w) @ P).toarray()
+        Hdiag = lambda: np.asarray(P.multiply(P).T @ w).ravel()
         # 1/2 sum_v w_v (P_v x - d_v)^2 = 1/2 x^T P^T W P x - (P^T W d)^T x + const
         p = np.array(spec.c, dtype=np.float64) - P.T @ (w * d)
     else:
@@ -105,7 +109,7 @@ def from_spec(spec) -> Problem:
         u = np.array(spec.uA, dtype=np.float64)
     C = np.zeros((0, n)) if spec.C is None else np.array(spec.C, dtype=np.float64)
     b = np.zeros(0) if spec.C is None else np.array(spec.b, dtype=np.float64)
-    return Problem(n, Hmul, Hdense, p, A, l, u, C, b,
+    return Problem(n, Hmul, Hdense, Hdiag, p, A, l, u, C, b,
                    np.array(spec.lx, dtype=np.float64), np.array(spec.ux, dtype=np.float64))
 
 
@@ -291,7 +295,7 @@ def jacobi_diagonal(prob: Problem, st: State, mu: float) -> np.ndarray:
     res = residuals(prob, st, mu)
     _, _, D, _, _, qb = reduced_system(prob, st, res, mu, with_Q=False)
     me, nl = prob.me, S.L.size
-    Hd = np.diag(prob.Hdense())
+    Hd = prob.Hdiag()
     Dinv = 1.0 / D
     BtDB = np.zeros(prob.n)
     if me:

@@ -54,7 +54,16 @@ struct qp_handle_s {
   int* hfl = nullptr;     // pinned host copy of fl
   int lpr_r = 16, lpr_x = 64, g_r = 1, g_x = 1, g_vec = 1, g_ts = 1, ts_chunk = 1, g_n = 1, g_ra = 1;
   std::vector<void*> allocs;
+  // optional event timing of PCG launches
+  struct Prof {
+    bool on = false;
+    int cap = 0;
+    std::vector<hipEvent_t> ev[QP_PROF_COUNT];  // 2 per launch
+    int used[QP_PROF_COUNT] = {0, 0, 0, 0};
+  } prof;
   ~qp_handle_s() {
+    for (int c = 0; c < QP_PROF_COUNT; ++c)
+      for (hipEvent_t e : prof.ev[c]) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (hsc) (void)hipHostFree(hsc);
     if (hfl) (void)hipHostFree(hfl);
@@ -194,6 +203,21 @@ static TsFinishArgs tsf_args(qp_handle h) {
   return a;
 }
 
+// Event bracket for one profiled launch (no-op unless profiling is on).
+struct ProfScope {
+  qp_handle h;
+  int cat;
+  int slot = -1;
+  ProfScope(qp_handle hh, int c, bool active) : h(hh), cat(c) {
+    if (!active || !h->prof.on || h->prof.used[c] >= h->prof.cap) return;
+    slot = h->prof.used[c]++;
+    (void)hipEventRecord(h->prof.ev[c][2 * slot], h->st);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(h->prof.ev[cat][2 * slot + 1], h->st);
+  }
+};
+
 // ---------------------------------------------------------------- steps
 // Step a1: residual stack at (x, lam, s, mu) and its norms (into sc).
 static qp_status run_residuals(qp_handle h) {
@@ -247,10 +271,14 @@ static qp_status prepare(qp_handle h) {
 static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, const int* done,
                             int* bump) {
   const int vk = lo ? h->vk : VK_F64;
+  const bool prof = bump != nullptr;  // only the PCG iteration's own matvec is timed
   if (h->has_ts) {
     TsArgs t = ts_args(h, lo, v);
     t.done = done;
-    HIPCHK(launch_ts_reduce(vk, t, h->g_ts, h->st));
+    {
+      ProfScope ps(h, QP_PROF_TSREDUCE, prof);
+      HIPCHK(launch_ts_reduce(vk, t, h->g_ts, h->st));
+    }
     TsFinishArgs f = tsf_args(h);
     f.we = h->we_mv; f.vl = v + h->n; f.yl = y + h->n;
     f.partout = h->part + P_DOT_TS * kGridMax; f.done = done;
@@ -260,12 +288,16 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     RowArgs a = row_args(h, lo);
     a.r0 = 0; a.r1 = h->nRP; a.v = v; a.vl = v + h->n; a.dl = h->dl; a.yl = y + h->n;
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
+    ProfScope ps(h, QP_PROF_ROWPASS, prof);
     HIPCHK(launch_rowpass(R_MATVEC, vk, h->lpr_r, a, h->g_r, h->st));
   }
   ColArgs c = col_args(h, lo);
   c.src_hx = v; c.src_pt = h->u; c.src_at = h->wA_mv; c.we = h->we_mv; c.v = v; c.y = y;
   c.part0 = h->part + P_DOT_X * kGridMax; c.done = done; c.bump = bump;
-  HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_x, h->st));
+  {
+    ProfScope ps(h, QP_PROF_COLPASS, prof);
+    HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_x, h->st));
+  }
   return QP_OK;
 }
 
@@ -306,6 +338,7 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
         HIPCHK(launch_cg_restart(a, h->tmp, h->st));
       }
       CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT));
+      ProfScope ps(h, QP_PROF_CGVEC, true);
       HIPCHK(launch_cg_update(a, h->st));
       HIPCHK(launch_cg_pupdate(a, h->st));
     }
@@ -1017,6 +1050,52 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c, double*
     HIPCHK(launch_rowpass(R_GRADW, VK_F64, h->lpr_r, a, h->g_r, h->st));
   }
   HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_profile_begin(qp_handle h, int32_t max_launches) {
+  if (!h || max_launches < 1) return QP_ERR_ARG;
+  for (int c = 0; c < QP_PROF_COUNT; ++c) {
+    for (hipEvent_t e : h->prof.ev[c]) (void)hipEventDestroy(e);
+    h->prof.ev[c].assign(2 * (size_t)max_launches, nullptr);
+    for (auto& e : h->prof.ev[c]) HIPCHK(hipEventCreate(&e));
+    h->prof.used[c] = 0;
+  }
+  h->prof.cap = max_launches;
+  h->prof.on = true;
+  return QP_OK;
+}
+
+qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms) {
+  if (!h || !h->prof.on) return QP_ERR_STATE;
+  HIPCHK(hipStreamSynchronize(h->st));
+  for (int c = 0; c < QP_PROF_COUNT; ++c) {
+    double tot = 0.0;
+    for (int i = 0; i < h->prof.used[c]; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, h->prof.ev[c][2 * i], h->prof.ev[c][2 * i + 1]));
+      tot += ms;
+    }
+    if (launches) launches[c] = h->prof.used[c];
+    if (total_ms) total_ms[c] = tot;
+    for (hipEvent_t e : h->prof.ev[c]) (void)hipEventDestroy(e);
+    h->prof.ev[c].clear();
+    h->prof.used[c] = 0;
+  }
+  h->prof.on = false;
+  h->prof.cap = 0;
+  return QP_OK;
+}
+
+qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
+                            int64_t* dense_bytes, int64_t* row_nnz, int64_t* col_nnz) {
+  if (!h) return QP_ERR_ARG;
+  const int64_t vb = h->vk == VK_F64 ? 8 : h->vk == VK_F32 ? 4 : 2;
+  if (row_bytes) *row_bytes = h->nnz_rp * (vb + 4) + 4 * (int64_t)(h->nRP + 1);
+  if (col_bytes) *col_bytes = h->nnz_xs * (vb + 4) + 12 * (int64_t)h->n + 4;
+  if (dense_bytes) *dense_bytes = (int64_t)h->n * h->k * vb;
+  if (row_nnz) *row_nnz = h->nnz_rp;
+  if (col_nnz) *col_nnz = h->nnz_xs;
   return QP_OK;
 }
 

@@ -81,7 +81,9 @@ EXPORTS = [
     "qp_create", "qp_destroy", "qp_set_stream", "qp_sizes", "qp_set_state", "qp_get_state",
     "qp_init_state", "qp_residuals", "qp_newton_rhs", "qp_kkt_matvec", "kkt_pcg_solve",
     "qp_newton_direction", "qp_step_lengths", "qp_take_step", "ipm_solve", "qp_backward",
+    "qp_profile_begin", "qp_profile_end", "qp_operator_bytes",
 ]
+PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "cgvec")
 
 
 def _load():
@@ -111,6 +113,9 @@ def _load():
         "qp_take_step": (C.c_int, [vp, vp, vp, vp, C.c_double, C.c_double]),
         "ipm_solve": (C.c_int, [vp, C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo)]),
         "qp_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.POINTER(PcgOptions), C.POINTER(PcgInfo)]),
+        "qp_profile_begin": (C.c_int, [vp, C.c_int32]),
+        "qp_profile_end": (C.c_int, [vp, _i64p, _dp]),
+        "qp_operator_bytes": (C.c_int, [vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -336,6 +341,21 @@ class QP:
             k = info.iterations
             logs = {key: v[:k].copy() for key, v in logs.items()}
         return dict(x=x, lam=lam, s=s, info=info, log=logs)
+
+    def profile_begin(self, max_launches: int):
+        self._check(LIB.qp_profile_begin(self.h, int(max_launches)))
+
+    def profile_end(self):
+        cnt = (C.c_int64 * 4)()
+        ms = (C.c_double * 4)()
+        self._check(LIB.qp_profile_end(self.h, cnt, ms))
+        return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(PROF_CATEGORIES)}
+
+    def operator_bytes(self):
+        v = [C.c_int64() for _ in range(5)]
+        self._check(LIB.qp_operator_bytes(self.h, *[C.byref(x) for x in v]))
+        return dict(zip(("row_bytes", "col_bytes", "dense_bytes", "row_nnz", "col_nnz"),
+                        [int(x.value) for x in v]))
 
     def backward(self, grad_x, want=("c", "lA", "uA", "b", "w"), opts: Optional[PcgOptions] = None):
         n, sz = self.sizes.n, self.sizes

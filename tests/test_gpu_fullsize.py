@@ -1,0 +1,77 @@
+"""Parity at the full radiation-therapy size (200,000 voxels x 20,000
+beamlets, 10,000 max-dose rows) in the launch configuration the benchmark
+times.  The dense oracle cannot run here, so the checks use the oracle's
+matrix-free functions (residuals, K v, Jacobi diagonal) and properties that
+hold at any size."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import (from_masked, kkt_from_masked, kkt_to_masked, rel,
+                           res_to_masked, to_masked)
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_2308_00637_amd.qpk import QP
+    spec = W.rt_full()
+    print(f"rt_full generated: nnz(P)={spec.P.nnz} nnz(A)={spec.A.nnz}", flush=True)
+    prob = O.from_spec(spec)
+    qp = QP(spec)
+    return spec, prob, qp
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def test_steps_at_start_point(full):
+    spec, prob, qp = full
+    qp.init_state(1.0)
+    st = O.initial_point(prob)
+    x, lam, s, mu = qp.get_state()
+    ex, el, es = to_masked(prob, st)
+    assert np.array_equal(x.cpu().numpy(), ex)
+    assert rel(s.cpu().numpy(), es) <= 1e-15 and np.array_equal(lam.cpu().numpy(), el)
+    r, norms = qp.residuals()
+    res = O.residuals(prob, st, 1.0)
+    assert rel(r.cpu().numpy(), res_to_masked(prob, res)) <= 1e-12
+    assert norms[0] == pytest.approx(O.stacked_norm(res), rel=1e-12)
+    rhs, dg = qp.newton_rhs()
+    ref_rhs, _ = O.newton_rhs_doubly(prob, st, 1.0)
+    assert rel(kkt_from_masked(prob, rhs.cpu().numpy()), ref_rhs) <= 1e-12
+    assert rel(kkt_from_masked(prob, dg.cpu().numpy()), O.jacobi_diagonal(prob, st, 1.0)) <= 1e-12
+    v = np.random.default_rng(0).standard_normal(ref_rhs.size)
+    y = qp.kkt_matvec(dev(kkt_to_masked(prob, v)))
+    assert rel(kkt_from_masked(prob, y.cpu().numpy()), O.kkt_matvec(prob, st, 1.0, v)) <= 1e-12
+    sol, info = qp.kkt_pcg_solve(rhs)
+    assert info.converged == 1
+    solc = kkt_from_masked(prob, sol.cpu().numpy())
+    true_rel = np.linalg.norm(ref_rhs - O.kkt_matvec(prob, st, 1.0, solc)) / np.linalg.norm(ref_rhs)
+    assert true_rel <= 1.5e-7, true_rel
+    assert info.rel_residual == pytest.approx(true_rel, rel=1e-6, abs=1e-12)
+
+
+def test_ipm_solve_kkt_by_oracle_function(full):
+    spec, prob, qp = full
+    out = qp.solve(log=True)
+    info = out["info"]
+    print(f"ipm={info.iterations} cg={info.total_cg_iters} caps={info.cg_maxiter_hits} "
+          f"time={info.time_ms / 1e3:.2f}s obj={info.objective:.10g} rnorm={info.rnorm:.3e}", flush=True)
+    assert info.result == 0 and info.mu_final < 1e-6
+    gst = from_masked(prob, out["x"].cpu().numpy(), out["lam"].cpu().numpy(), out["s"].cpu().numpy())
+    res = O.residuals(prob, gst, info.mu_final)
+    kkt = O.stacked_norm(res)
+    assert kkt <= 1e-6 and kkt == pytest.approx(info.rnorm, rel=1e-9)
+    assert info.objective == pytest.approx(O.objective(prob, gst.x), rel=1e-12)
+    # primal feasibility of the returned point: x >= 0 and the max-dose rows
+    assert gst.x.min() >= -1e-6
+    assert (spec.A @ gst.x).max() <= 1.1 + 1e-6
+    # duality gap of the returned point bounds its distance to the optimum:
+    # f(x) - f* <= sum(lam * s) + O(||r||)
+    gap = float(gst.lam_uA @ gst.s_uA + gst.lam_lx @ gst.s_lx)
+    assert gap <= 1e-6 * (prob.n + prob.m) * 10

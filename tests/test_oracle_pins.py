@@ -106,10 +106,13 @@ def test_kkt_is_spd_along_the_iterates():
 
 
 # ----------------------------------------------- operator, Jacobi (P4, P5)
-@pytest.mark.parametrize("h_kind", ["dense", "lowrank"])
+@pytest.mark.parametrize("h_kind", ["dense", "lowrank", "ptwp"])
 def test_matrix_free_operator_and_jacobi(h_kind):
     rng = np.random.default_rng(11)
-    prob = general(6, a_sparse=True, h_kind=h_kind)
+    if h_kind == "ptwp":
+        prob = O.from_spec(W.rt_qp(8, 90, 12, 0.2, 7, maxdose=0.5))
+    else:
+        prob = general(6, a_sparse=True, h_kind=h_kind)
     st = random_state(prob, rng)
     mu = 0.3
     res = O.residuals(prob, st, mu)
