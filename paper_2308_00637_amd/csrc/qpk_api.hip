@@ -53,6 +53,20 @@ struct qp_handle_s {
   double* hsc = nullptr;  // pinned host copy of sc
   int* hfl = nullptr;     // pinned host copy of fl
   int lpr_r = 16, lpr_x = 64, g_r = 1, g_x = 1, g_vec = 1, g_ts = 1, ts_chunk = 1, g_n = 1, g_ra = 1;
+  // LDS-staged blocked PCG matvec passes
+  struct Chunked {
+    bool on = false;
+    int nrows = 0, ncols = 0, nchunk = 0, nwork = 0, lpr = 16;
+    int32_t* work = nullptr;
+    int32_t* rowptr = nullptr;
+    uint16_t* col = nullptr;
+    double* val = nullptr;
+    void* val_lo = nullptr;
+    double* partial = nullptr;
+    int64_t nnz = 0;
+  } ck_r, ck_x;
+  int g_rmv = 1, g_xmv = 1, g_epi = 1;  // partial counts of the PCG matvec passes
+  double* uw = nullptr;  // [u (p_rows) | wA (m)] for the PCG matvec
   std::vector<void*> allocs;
   // optional event timing of PCG launches
   struct Prof {
@@ -266,6 +280,15 @@ static qp_status prepare(qp_handle h) {
   return QP_OK;
 }
 
+static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double* src) {
+  ChunkArgs c{};
+  c.nrows = k.nrows; c.ncols = k.ncols; c.nchunk = k.nchunk;
+  c.work = k.work; c.rowptr = k.rowptr; c.col = k.col;
+  c.val = lo ? k.val_lo : (const void*)k.val;
+  c.src = src; c.partial = k.partial;
+  return c;
+}
+
 // Step a4: y = K v (v, y: K-vectors).  lo selects the reduced-precision
 // operator copies.  done/bump: PCG early exit and iteration counter.
 static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, const int* done,
@@ -289,14 +312,36 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     a.r0 = 0; a.r1 = h->nRP; a.v = v; a.vl = v + h->n; a.dl = h->dl; a.yl = y + h->n;
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
     ProfScope ps(h, QP_PROF_ROWPASS, prof);
-    HIPCHK(launch_rowpass(R_MATVEC, vk, h->lpr_r, a, h->g_r, h->st));
+    if (h->ck_r.on) {
+      ChunkArgs ca = chunk_args(h->ck_r, lo, v);
+      if (h->ck_r.nchunk == 1) {
+        HIPCHK(launch_chunked(CE_ROW, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st));
+      } else {
+        HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st));
+        HIPCHK(launch_chunk_epilogue_row(ca, a, h->g_epi, h->st));
+      }
+    } else {
+      HIPCHK(launch_rowpass(R_MATVEC, vk, h->lpr_r, a, h->g_rmv, h->st));
+    }
   }
   ColArgs c = col_args(h, lo);
   c.src_hx = v; c.src_pt = h->u; c.src_at = h->wA_mv; c.we = h->we_mv; c.v = v; c.y = y;
   c.part0 = h->part + P_DOT_X * kGridMax; c.done = done; c.bump = bump;
   {
     ProfScope ps(h, QP_PROF_COLPASS, prof);
-    HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_x, h->st));
+    if (h->ck_x.on) {
+      ChunkArgs ca = chunk_args(h->ck_x, lo, h->uw);
+      if (h->ck_x.nchunk == 1) {
+        HIPCHK(launch_chunked(CE_COL, vk, h->ck_x.lpr, ca, RowArgs{}, c, h->ck_x.nwork, h->st));
+      } else {
+        ColArgs c0 = c;
+        c0.bump = nullptr;
+        HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_x.lpr, ca, RowArgs{}, c0, h->ck_x.nwork, h->st));
+        HIPCHK(launch_chunk_epilogue_col(ca, c, h->g_epi, h->st));
+      }
+    } else {
+      HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_xmv, h->st));
+    }
   }
   return QP_OK;
 }
@@ -306,7 +351,7 @@ static CgArgs cg_args(qp_handle h, const double* rhs, double* sol, const pcg_opt
   a.N = (int32_t)h->N(); a.n = h->n;
   a.x = sol; a.r = h->cg_r; a.z = h->cg_z; a.p = h->cg_p; a.q = h->cg_q;
   a.rhs = rhs; a.jdiag = h->jdiag; a.part = h->part; a.fl = h->fl; a.sc = h->sc;
-  a.g_vec = h->g_vec; a.g_r = h->nRP > 0 ? h->g_r : 0; a.g_x = h->g_x; a.has_ts = h->has_ts;
+  a.g_vec = h->g_vec; a.g_r = h->nRP > 0 ? h->g_rmv : 0; a.g_x = h->g_xmv; a.has_ts = h->has_ts;
   a.tol = o.tol; a.maxit = o.maxit;
   return a;
 }
@@ -465,6 +510,83 @@ static thread_local std::string g_create_error;
 
 const char* qp_last_error(qp_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
+// Split a CSR operator (sorted columns in [0, ncols)) into column chunks of
+// kChunkCols with uint16 in-chunk offsets, stored chunk-major, and cut each
+// chunk's rows into work items of about equal entry counts so that all items
+// fit one wave of blocks (one block per CU, 256 CUs).
+static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
+                               const std::vector<int32_t>& col, const std::vector<double>& val,
+                               int ncols) {
+  const int64_t nrows = (int64_t)rp.size() - 1;
+  const int nchunk = (int)std::max<int64_t>(1, (ncols + kChunkCols - 1) / kChunkCols);
+  const int64_t nnz = rp[nrows];
+  std::vector<int64_t> cnt((size_t)nchunk * nrows, 0);
+  for (int64_t r = 0; r < nrows; ++r)
+    for (int64_t q = rp[r]; q < rp[r + 1]; ++q) cnt[(size_t)(col[q] / kChunkCols) * nrows + r]++;
+  std::vector<int32_t> crp((size_t)nchunk * (nrows + 1));
+  std::vector<int64_t> cnnz(nchunk, 0);
+  int64_t off = 0;
+  for (int c = 0; c < nchunk; ++c) {
+    for (int64_t r = 0; r < nrows; ++r) {
+      crp[(size_t)c * (nrows + 1) + r] = (int32_t)off;
+      off += cnt[(size_t)c * nrows + r];
+    }
+    crp[(size_t)c * (nrows + 1) + nrows] = (int32_t)off;
+    cnnz[c] = crp[(size_t)c * (nrows + 1) + nrows] - crp[(size_t)c * (nrows + 1)];
+  }
+  std::vector<uint16_t> ccol(nnz);
+  std::vector<double> cval(nnz);
+  {
+    std::vector<int64_t> cur(cnt.size());
+    for (int c = 0; c < nchunk; ++c)
+      for (int64_t r = 0; r < nrows; ++r) cur[(size_t)c * nrows + r] = crp[(size_t)c * (nrows + 1) + r];
+    for (int64_t r = 0; r < nrows; ++r)
+      for (int64_t q = rp[r]; q < rp[r + 1]; ++q) {
+        const int c = col[q] / kChunkCols;
+        const int64_t pos = cur[(size_t)c * nrows + r]++;
+        ccol[pos] = (uint16_t)(col[q] - c * kChunkCols);
+        cval[pos] = val[q];
+      }
+  }
+  // work items: per chunk, proportional to its entries, rows cut at equal entry counts
+  const int target = std::max(nchunk, 256 - nchunk);
+  std::vector<int32_t> work;
+  for (int c = 0; c < nchunk; ++c) {
+    const int items = (int)std::max<int64_t>(1, nnz > 0 ? (int64_t)target * cnnz[c] / nnz : 1);
+    const int32_t* base = &crp[(size_t)c * (nrows + 1)];
+    int64_t r = 0;
+    for (int it = 0; it < items; ++it) {
+      const int64_t goal = base[0] + (cnnz[c] * (it + 1)) / items;
+      int64_t r1 = r;
+      while (r1 < nrows && (base[r1 + 1] <= goal || r1 == r)) ++r1;
+      if (it == items - 1) r1 = nrows;
+      if (r1 > r || it == items - 1) {
+        work.push_back(c);
+        work.push_back((int32_t)r);
+        work.push_back((int32_t)r1);
+      }
+      r = r1;
+      if (r >= nrows) break;
+    }
+  }
+  ck.nrows = (int)nrows;
+  ck.ncols = ncols;
+  ck.nchunk = nchunk;
+  ck.nwork = (int)(work.size() / 3);
+  ck.nnz = nnz;
+  const double avg = nrows > 0 ? (double)nnz / ((double)nrows * nchunk) : 1.0;
+  ck.lpr = pow2_clamp(avg / 4.0, 4, 64);
+  CHK(upload(h, &ck.work, work.data(), (int64_t)work.size()));
+  CHK(upload(h, &ck.rowptr, crp.data(), (int64_t)crp.size()));
+  CHK(upload(h, &ck.col, ccol.data(), nnz));
+  CHK(upload(h, &ck.val, cval.data(), nnz));
+  if (h->vk != VK_F64) CHK(upload_lo(h, &ck.val_lo, cval));
+  if (nchunk > 1) CHK(dalloc_t(h, &ck.partial, (int64_t)nchunk * nrows));
+  HIPCHK(hipStreamSynchronize(h->st));  // host staging vectors go out of scope
+  ck.on = true;
+  return QP_OK;
+}
+
 static qp_status create_impl(qp_handle h, const qp_desc* d) {
   const int64_t n = d->n, m = d->m, me = d->me;
   auto bad = [&](const std::string& msg) { h->err = msg; return QP_ERR_ARG; };
@@ -620,6 +742,19 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   h->has_xs = acc > 0;
   h->has_ts = k > 0 || me > 0;
 
+  // LDS-staged blocked copies of the two PCG matvec operators.  The column
+  // side needs one gathered vector per entry, so it is built when H has no
+  // dense or low-rank part: its columns index [u (p_rows) | wA (m)].
+  const bool want_ck_x = acc > 0 && hnnz == 0 && k == 0;
+  std::vector<int32_t> scol;
+  if (want_ck_x) {
+    scol.resize(acc);
+    for (int64_t j = 0; j < n; ++j) {
+      for (int64_t q = xs1[j]; q < xs2[j]; ++q) scol[q] = xcol[q];
+      for (int64_t q = xs2[j]; q < xrp[j + 1]; ++q) scol[q] = (int32_t)(p_rows + xcol[q]);
+    }
+  }
+
   // Launch shapes
   const double avg_r = h->nRP > 0 ? (double)h->nnz_rp / h->nRP : 0.0;
   const double avg_x = (double)acc / n + (double)k;
@@ -629,6 +764,8 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   h->g_ra = grid_cap((int64_t)std::max<int64_t>(m, 1) * h->lpr_r, kBlock, kGridMax);
   h->g_x = grid_cap(n * (int64_t)h->lpr_x, kBlock, kGridMax);
   h->g_vec = grid_cap(h->N(), kBlock, 512);
+  h->g_rmv = h->g_r;
+  h->g_xmv = h->g_x;
   h->g_n = grid_cap(n, kBlock, kGridMax);
   h->g_ts = (int)std::max<int64_t>(1, std::min<int64_t>(kGridMax, (n + 63) / 64));
   h->ts_chunk = (int)((n + h->g_ts - 1) / h->g_ts);
@@ -642,6 +779,12 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(upload(h, &h->xs_seg2, xs2.data(), (int64_t)xs2.size()));
   CHK(upload(h, &h->xs_col, xcol.data(), (int64_t)xcol.size()));
   CHK(upload(h, &h->xs_val, xval.data(), (int64_t)xval.size()));
+  HIPCHK(chunked_set_attributes());
+  if (h->nRP > 0) CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n));
+  if (want_ck_x) CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m)));
+  h->g_epi = grid_cap(std::max<int64_t>(n, h->nRP), kBlock, kGridMax);
+  if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi;
+  if (h->ck_x.on) h->g_xmv = h->ck_x.nchunk == 1 ? h->ck_x.nwork : h->g_epi;
   if (k > 0) {
     CHK(upload(h, &h->U, d->U, n * k));
     CHK(upload(h, &h->wd, d->wd, k));
@@ -695,7 +838,8 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(dalloc_t(h, &h->jdiag, N));
   CHK(dalloc_t(h, &h->dl, me + 2 * m));
   CHK(dalloc_t(h, &h->qdiag, n));
-  CHK(dalloc_t(h, &h->wA_mv, m));
+  CHK(dalloc_t(h, &h->uw, p_rows + m));
+  h->wA_mv = h->uw + p_rows;
   CHK(dalloc_t(h, &h->wA_res, m));
   CHK(dalloc_t(h, &h->wA_rhs, m));
   CHK(dalloc_t(h, &h->jw, m));
@@ -704,7 +848,7 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(dalloc_t(h, &h->we_rhs, me));
   CHK(dalloc_t(h, &h->te, me));
   CHK(dalloc_t(h, &h->g, k));
-  CHK(dalloc_t(h, &h->u, p_rows));
+  h->u = h->uw;
   CHK(dalloc_t(h, &h->cg_r, N));
   CHK(dalloc_t(h, &h->cg_z, N));
   CHK(dalloc_t(h, &h->cg_p, N));
@@ -1091,8 +1235,14 @@ qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
                             int64_t* dense_bytes, int64_t* row_nnz, int64_t* col_nnz) {
   if (!h) return QP_ERR_ARG;
   const int64_t vb = h->vk == VK_F64 ? 8 : h->vk == VK_F32 ? 4 : 2;
-  if (row_bytes) *row_bytes = h->nnz_rp * (vb + 4) + 4 * (int64_t)(h->nRP + 1);
-  if (col_bytes) *col_bytes = h->nnz_xs * (vb + 4) + 12 * (int64_t)h->n + 4;
+  // bytes of the structures the PCG matvec streams (values, column indices, row pointers)
+  auto ck_bytes = [&](const qp_handle_s::Chunked& k) {
+    return k.nnz * (vb + 2) + 4 * (int64_t)k.nchunk * (k.nrows + 1);
+  };
+  if (row_bytes)
+    *row_bytes = h->ck_r.on ? ck_bytes(h->ck_r) : h->nnz_rp * (vb + 4) + 4 * (int64_t)(h->nRP + 1);
+  if (col_bytes)
+    *col_bytes = h->ck_x.on ? ck_bytes(h->ck_x) : h->nnz_xs * (vb + 4) + 12 * (int64_t)h->n + 4;
   if (dense_bytes) *dense_bytes = (int64_t)h->n * h->k * vb;
   if (row_nnz) *row_nnz = h->nnz_rp;
   if (col_nnz) *col_nnz = h->nnz_xs;

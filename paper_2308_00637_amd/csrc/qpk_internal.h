@@ -14,7 +14,7 @@
 namespace qpk {
 
 constexpr int kBlock = 256;      // threads per block for every kernel
-constexpr int kGridMax = 1024;   // cap on blocks of grid-stride kernels (= partial slots)
+constexpr int kGridMax = 2048;   // cap on blocks of grid-stride kernels (= partial slots)
 constexpr int QP_ERR_NOT_SPD_CODE = -4;   // mirrors qp_status in qpk.h
 constexpr int QP_ERR_NUMERIC_CODE = -5;
 
@@ -127,6 +127,31 @@ struct TsArgs {
 hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid, hipStream_t st);
 hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid, hipStream_t st);
 hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st);
+
+// LDS-staged 2-D blocked passes.  The columns of a CSR operator are cut into
+// chunks of kChunkCols; chunk c stores its own CSR (rowptr c*(nrows+1) ...,
+// uint16 column offsets within the chunk).  A block takes one work item
+// (chunk, first row, end row), copies that chunk of the gathered vector into
+// LDS and reduces its rows from there.  With one chunk the row epilogue runs in
+// place; otherwise per-chunk partial sums are written and an epilogue kernel
+// adds them in chunk order.
+constexpr int kChunkBlock = 1024;                 // threads per block
+constexpr int kChunkCols = 20224;                 // float64 values per LDS chunk
+struct ChunkArgs {
+  int32_t nrows, ncols, nchunk;
+  const int32_t* work;       // 3 per block: chunk, r0, r1
+  const int32_t* rowptr;     // nchunk * (nrows + 1)
+  const uint16_t* col;
+  const void* val;
+  const double* src;         // gathered vector (ncols)
+  double* partial;           // nchunk * nrows when nchunk > 1
+};
+enum ChunkEpi : int { CE_PARTIAL = 0, CE_ROW = 1, CE_COL = 2 };
+hipError_t launch_chunked(int epi, int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
+                          const ColArgs& ca, int nwork, hipStream_t st);
+hipError_t launch_chunk_epilogue_col(const ChunkArgs& c, const ColArgs& ca, int grid, hipStream_t st);
+hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int grid, hipStream_t st);
+hipError_t chunked_set_attributes();
 
 }  // namespace qpk
 

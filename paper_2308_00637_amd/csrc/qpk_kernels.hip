@@ -337,6 +337,148 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
   }
 }
 
+// ------------------------------------------------ matvec epilogues
+// Matvec epilogues shared by the PCG passes.
+// Row epilogue of the PCG matvec (R_MATVEC): P rows give u = w t; A rows give
+// the lam-part of K v and wA = w_l - w_u.  Returns the row's p_lam . q_lam.
+__device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row, double td) {
+  if (row < a.p_rows) {
+    a.u[row] = a.w[row] * td;
+    return 0.0;
+  }
+  const int i = row - a.p_rows, me = a.me, m = a.m;
+  const bool hl = has_lo(a.lA[i]), hu = has_hi(a.uA[i]);
+  const double vlo = a.vl[me + i], vup = a.vl[me + m + i];
+  const double dlo = a.dl[me + i], dup = a.dl[me + m + i];
+  const double ylo = (hl ? td : 0.0) + dlo * vlo;
+  const double yup = (hu ? -td : 0.0) + dup * vup;
+  a.yl[me + i] = ylo;
+  a.yl[me + m + i] = yup;
+  a.wA[i] = (hl ? 2.0 * td / dlo + vlo : 0.0) - (hu ? -2.0 * td / dup + vup : 0.0);
+  return vlo * ylo + vup * yup;
+}
+
+// Column epilogue of the PCG matvec (X_MATVEC); returns v_j y_j.
+__device__ __forceinline__ double col_matvec_epilogue(const ColArgs& a, int j, double y) {
+  for (int e = 0; e < a.me; ++e) y += a.Cm[static_cast<int64_t>(e) * a.n + j] * a.we[e];
+  const double vj = a.v[j];
+  y += a.qdiag[j] * vj;
+  a.y[j] = y;
+  return vj * y;
+}
+
+// ------------------------------------------- LDS-staged blocked passes
+template <int NT>
+__device__ double block_sum_nt(double v) {
+  __shared__ double sh[NT / 64];
+  v = group_sum<64>(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+template <int EPI, int VK, int LPR>
+__global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra, ColArgs ca) {
+  using T = typename VT<VK>::T;
+  using Acc = typename VT<VK>::Acc;
+  if ((ra.done && *ra.done) || (ca.done && *ca.done)) return;
+  if constexpr (EPI == CE_COL) {
+    if (ca.bump && blockIdx.x == 0 && threadIdx.x == 0) *ca.bump += 1;
+  }
+  extern __shared__ double lds[];
+  const int c = b.work[3 * blockIdx.x], r0 = b.work[3 * blockIdx.x + 1], r1 = b.work[3 * blockIdx.x + 2];
+  const int c0 = c * kChunkCols;
+  const int cw = min(kChunkCols, b.ncols - c0);
+  for (int j = threadIdx.x; j < cw; j += kChunkBlock) lds[j] = b.src[c0 + j];
+  __syncthreads();
+  const int32_t* __restrict__ rp = b.rowptr + static_cast<int64_t>(c) * (b.nrows + 1);
+  const uint16_t* __restrict__ col = b.col;
+  const T* __restrict__ val = static_cast<const T*>(b.val);
+  const int lane = threadIdx.x & (LPR - 1);
+  const int gid = threadIdx.x / LPR;
+  constexpr int NG = kChunkBlock / LPR;
+  constexpr int PER = 8;  // entries per lane per step: a whole row's loads in flight
+  double acc0 = 0.0;
+  int row = r0 + gid;
+  int beg = 0, end = 0;
+  if (row < r1) {
+    beg = rp[row];
+    end = rp[row + 1];
+  }
+  for (; row < r1; row += NG) {
+    // prefetch the next row's bounds while this row's entries load
+    const int nrow = row + NG;
+    int nbeg = 0, nend = 0;
+    if (nrow < r1) {
+      nbeg = rp[nrow];
+      nend = rp[nrow + 1];
+    }
+    Acc t = 0;
+    for (int base = beg; base < end; base += LPR * PER) {
+      int ci[PER];
+      Acc vv[PER];
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int q = base + lane + k * LPR;
+        const bool ok = q < end;
+        ci[k] = ok ? static_cast<int>(col[q]) : 0;
+        vv[k] = ok ? ldv(val, q) : Acc(0);
+      }
+#pragma unroll
+      for (int k = 0; k < PER; ++k) t += vv[k] * static_cast<Acc>(lds[ci[k]]);
+    }
+    t = group_sum<LPR>(t);
+    if (lane == 0) {
+      const double td = static_cast<double>(t);
+      if constexpr (EPI == CE_PARTIAL) b.partial[static_cast<int64_t>(c) * b.nrows + row] = td;
+      else if constexpr (EPI == CE_ROW) acc0 += row_matvec_epilogue(ra, row, td);
+      else acc0 += col_matvec_epilogue(ca, row, td);
+    }
+    beg = nbeg;
+    end = nend;
+  }
+  if constexpr (EPI != CE_PARTIAL) {
+    acc0 = block_sum_nt<kChunkBlock>(acc0);
+    if (threadIdx.x == 0) {
+      if constexpr (EPI == CE_ROW) ra.part0[blockIdx.x] = acc0;
+      else ca.part0[blockIdx.x] = acc0;
+    }
+  }
+}
+
+// Sum of the per-chunk partials in chunk order, then the matvec epilogue.
+__global__ __launch_bounds__(kBlock) void k_chunk_epilogue_col(ChunkArgs b, ColArgs a) {
+  if (a.done && *a.done) return;
+  if (a.bump && blockIdx.x == 0 && threadIdx.x == 0) *a.bump += 1;
+  double acc0 = 0.0;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < b.nrows; j += gridDim.x * kBlock) {
+    double y = 0.0;
+    for (int c = 0; c < b.nchunk; ++c) y += b.partial[static_cast<int64_t>(c) * b.nrows + j];
+    acc0 += col_matvec_epilogue(a, j, y);
+  }
+  acc0 = block_sum(acc0);
+  if (threadIdx.x == 0) a.part0[blockIdx.x] = acc0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_epilogue_row(ChunkArgs b, RowArgs a) {
+  if (a.done && *a.done) return;
+  double acc0 = 0.0;
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < b.nrows; r += gridDim.x * kBlock) {
+    double t = 0.0;
+    for (int c = 0; c < b.nchunk; ++c) t += b.partial[static_cast<int64_t>(c) * b.nrows + r];
+    acc0 += row_matvec_epilogue(a, r, t);
+  }
+  acc0 = block_sum(acc0);
+  if (threadIdx.x == 0) a.part0[blockIdx.x] = acc0;
+}
+
 // ------------------------------------------ tall-skinny dense reduction
 // Block b reduces rows [b*chunk, (b+1)*chunk) of U (n x k, row-major) into
 // part[b][0..k) and of C (me x n) into part[b][k..k+me).  Each wave owns a
@@ -838,6 +980,75 @@ hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid,
     case X_OBJ: return colpass_lpr<X_OBJ, VK_F64>(lpr, a, grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int EPI, int VK>
+static hipError_t chunked_lpr(int lpr, const ChunkArgs& c, const RowArgs& ra, const ColArgs& ca,
+                              int nwork, hipStream_t st) {
+  const size_t lds = sizeof(double) * kChunkCols;
+  switch (lpr) {
+    case 4: k_chunked<EPI, VK, 4><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
+    case 8: k_chunked<EPI, VK, 8><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
+    case 16: k_chunked<EPI, VK, 16><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
+    case 32: k_chunked<EPI, VK, 32><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
+    default: k_chunked<EPI, VK, 64><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
+  }
+  return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t chunked_vk(int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
+                             const ColArgs& ca, int nwork, hipStream_t st) {
+  if (vk == VK_F32) return chunked_lpr<EPI, VK_F32>(lpr, c, ra, ca, nwork, st);
+  if (vk == VK_BF16) return chunked_lpr<EPI, VK_BF16>(lpr, c, ra, ca, nwork, st);
+  return chunked_lpr<EPI, VK_F64>(lpr, c, ra, ca, nwork, st);
+}
+
+hipError_t launch_chunked(int epi, int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
+                          const ColArgs& ca, int nwork, hipStream_t st) {
+  if (epi == CE_ROW) return chunked_vk<CE_ROW>(vk, lpr, c, ra, ca, nwork, st);
+  if (epi == CE_COL) return chunked_vk<CE_COL>(vk, lpr, c, ra, ca, nwork, st);
+  return chunked_vk<CE_PARTIAL>(vk, lpr, c, ra, ca, nwork, st);
+}
+
+template <int EPI, int VK>
+static hipError_t set_attr_lpr() {
+  const int lds = sizeof(double) * kChunkCols;
+  hipError_t e = hipSuccess;
+  auto one = [&](const void* f) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  };
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 4>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 8>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 16>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 32>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 64>));
+  return e;
+}
+
+hipError_t chunked_set_attributes() {
+  hipError_t e = hipSuccess;
+  auto chain = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chain(set_attr_lpr<CE_PARTIAL, VK_F64>());
+  chain(set_attr_lpr<CE_PARTIAL, VK_F32>());
+  chain(set_attr_lpr<CE_PARTIAL, VK_BF16>());
+  chain(set_attr_lpr<CE_ROW, VK_F64>());
+  chain(set_attr_lpr<CE_ROW, VK_F32>());
+  chain(set_attr_lpr<CE_ROW, VK_BF16>());
+  chain(set_attr_lpr<CE_COL, VK_F64>());
+  chain(set_attr_lpr<CE_COL, VK_F32>());
+  chain(set_attr_lpr<CE_COL, VK_BF16>());
+  return e;
+}
+
+hipError_t launch_chunk_epilogue_col(const ChunkArgs& c, const ColArgs& ca, int grid, hipStream_t st) {
+  k_chunk_epilogue_col<<<grid, kBlock, 0, st>>>(c, ca);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int grid, hipStream_t st) {
+  k_chunk_epilogue_row<<<grid, kBlock, 0, st>>>(c, ra);
+  return hipGetLastError();
 }
 
 hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st) {
