@@ -48,6 +48,7 @@ struct qp_handle_s {
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *tmp = nullptr;
   double *dir = nullptr, *ds_w = nullptr;   // dir = [dx | dlam] (n + me + 2m + 2n)
   double* arhs = nullptr;                    // adjoint right-hand side
+  double* valign = nullptr;                  // 16-byte aligned copy of a caller vector
   double *part = nullptr, *ts_part = nullptr, *sc = nullptr;
   int* fl = nullptr;
   double* hsc = nullptr;  // pinned host copy of sc
@@ -295,6 +296,11 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
                             int* bump) {
   const int vk = lo ? h->vk : VK_F64;
   const bool prof = bump != nullptr;  // only the PCG iteration's own matvec is timed
+  if (reinterpret_cast<uintptr_t>(v) & 15) {
+    // the blocked row pass stages v with 16-byte loads
+    HIPCHK(launch_copy(v, h->valign, h->N(), 1.0, h->st));
+    v = h->valign;
+  }
   if (h->has_ts) {
     TsArgs t = ts_args(h, lo, v);
     t.done = done;
@@ -855,6 +861,7 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(dalloc_t(h, &h->cg_q, N));
   CHK(dalloc_t(h, &h->tmp, N));
   CHK(dalloc_t(h, &h->arhs, N));
+  CHK(dalloc_t(h, &h->valign, N));
   CHK(dalloc_t(h, &h->dir, n + h->nlam()));
   CHK(dalloc_t(h, &h->ds_w, h->ns()));
   CHK(dalloc_t(h, &h->part, (int64_t)P_COUNT * kGridMax));

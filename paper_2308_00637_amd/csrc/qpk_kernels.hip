@@ -392,47 +392,80 @@ __global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra
   if constexpr (EPI == CE_COL) {
     if (ca.bump && blockIdx.x == 0 && threadIdx.x == 0) *ca.bump += 1;
   }
-  extern __shared__ double lds[];
+  extern __shared__ __align__(16) double lds[];
   const int c = b.work[3 * blockIdx.x], r0 = b.work[3 * blockIdx.x + 1], r1 = b.work[3 * blockIdx.x + 2];
-  const int c0 = c * kChunkCols;
-  const int cw = min(kChunkCols, b.ncols - c0);
-  for (int j = threadIdx.x; j < cw; j += kChunkBlock) lds[j] = b.src[c0 + j];
-  __syncthreads();
   const int32_t* __restrict__ rp = b.rowptr + static_cast<int64_t>(c) * (b.nrows + 1);
   const uint16_t* __restrict__ col = b.col;
   const T* __restrict__ val = static_cast<const T*>(b.val);
   const int lane = threadIdx.x & (LPR - 1);
   const int gid = threadIdx.x / LPR;
   constexpr int NG = kChunkBlock / LPR;
-  constexpr int PER = 8;  // entries per lane per step: a whole row's loads in flight
-  double acc0 = 0.0;
+  constexpr int PER = 8;                     // entries per lane per batch
+  constexpr int SPAN = LPR * PER;            // entries per group per batch
+
+  // Row bounds of this group's first row, then every staging load at once
+  // (16-byte loads), so the block waits for one memory latency, not twenty.
   int row = r0 + gid;
   int beg = 0, end = 0;
   if (row < r1) {
     beg = rp[row];
     end = rp[row + 1];
   }
+  const int c0 = c * kChunkCols;
+  const int cw = min(kChunkCols, b.ncols - c0);
+  constexpr int SP = (kChunkCols + 2 * kChunkBlock - 1) / (2 * kChunkBlock);
+  const double2* __restrict__ s2 = reinterpret_cast<const double2*>(b.src + c0);
+  double2 st[SP];
+#pragma unroll
+  for (int k = 0; k < SP; ++k) {
+    const int i2 = threadIdx.x + k * kChunkBlock;
+    st[k] = 2 * i2 + 1 < cw ? s2[i2] : make_double2(0.0, 0.0);
+  }
+  // first batch of the first row, in flight together with the staging loads
+  int ci[PER];
+  Acc vv[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int q = beg + lane + k * LPR;
+    const bool ok = q < end;
+    ci[k] = ok ? static_cast<int>(col[q]) : 0;
+    vv[k] = ok ? ldv(val, q) : Acc(0);
+  }
+#pragma unroll
+  for (int k = 0; k < SP; ++k) {
+    const int i2 = threadIdx.x + k * kChunkBlock;
+    if (2 * i2 + 1 < cw) reinterpret_cast<double2*>(lds)[i2] = st[k];
+  }
+  if ((cw & 1) && threadIdx.x == 0) lds[cw - 1] = b.src[c0 + cw - 1];
+  __syncthreads();
+
+  double acc0 = 0.0;
   for (; row < r1; row += NG) {
-    // prefetch the next row's bounds while this row's entries load
+    // next row: bounds and first batch issued before this row is reduced
     const int nrow = row + NG;
     int nbeg = 0, nend = 0;
     if (nrow < r1) {
       nbeg = rp[nrow];
       nend = rp[nrow + 1];
     }
+    int nci[PER];
+    Acc nvv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int q = nbeg + lane + k * LPR;
+      const bool ok = q < nend;
+      nci[k] = ok ? static_cast<int>(col[q]) : 0;
+      nvv[k] = ok ? ldv(val, q) : Acc(0);
+    }
     Acc t = 0;
-    for (int base = beg; base < end; base += LPR * PER) {
-      int ci[PER];
-      Acc vv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) t += vv[k] * static_cast<Acc>(lds[ci[k]]);
+    for (int base = beg + SPAN; base < end; base += SPAN) {   // rows longer than one batch
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int q = base + lane + k * LPR;
-        const bool ok = q < end;
-        ci[k] = ok ? static_cast<int>(col[q]) : 0;
-        vv[k] = ok ? ldv(val, q) : Acc(0);
+        if (q < end) t += ldv(val, q) * static_cast<Acc>(lds[col[q]]);
       }
-#pragma unroll
-      for (int k = 0; k < PER; ++k) t += vv[k] * static_cast<Acc>(lds[ci[k]]);
     }
     t = group_sum<LPR>(t);
     if (lane == 0) {
@@ -443,6 +476,11 @@ __global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra
     }
     beg = nbeg;
     end = nend;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      ci[k] = nci[k];
+      vv[k] = nvv[k];
+    }
   }
   if constexpr (EPI != CE_PARTIAL) {
     acc0 = block_sum_nt<kChunkBlock>(acc0);
