@@ -315,7 +315,11 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
   }
   if (h->nRP > 0) {
     RowArgs a = row_args(h, lo);
-    a.r0 = 0; a.r1 = h->nRP; a.v = v; a.vl = v + h->n; a.dl = h->dl; a.yl = y + h->n;
+    // the lam-part pointers are only dereferenced for rows of A; without them
+    // (m == 0) they point at valid memory for the blocked pass's clamped loads
+    a.r0 = 0; a.r1 = h->nRP; a.v = v;
+    a.vl = h->m > 0 ? v + h->n : v;
+    a.dl = h->dl; a.yl = y + h->n;
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
     ProfScope ps(h, QP_PROF_ROWPASS, prof);
     if (h->ck_r.on) {
