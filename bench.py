@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rt_full",
                     choices=["rt_full", "rt_small", "svm_full", "tiny_dense"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16", "fp32x64", "bf16x64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle PCG iterations for the CPU baseline (0: pick ~15 s)")
@@ -150,7 +150,7 @@ def main():
     solve_s = sum(i.time_ms for i in infos) / 1e3
     info = infos[-1]
 
-    prec_bytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    prec_bytes = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32x64": 4, "bf16x64": 2}[args.precision]
     kern = {}
     for cat in ("rowpass", "colpass", "tsreduce"):
         cnt, ms = prof[cat]
@@ -183,6 +183,7 @@ def main():
         "ipm_iterations": info.iterations,
         "pcg_iterations_per_solve": total_cg / args.steps,
         "cg_maxiter_hits": info.cg_maxiter_hits,
+        "cg_escalations_to_fp64": info.cg_escalations,
         "kkt_residual": info.rnorm,
         "objective": info.objective,
         "mu_final": info.mu_final,

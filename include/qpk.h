@@ -64,10 +64,17 @@ typedef enum {
 
 typedef enum { QP_H_DENSE = 0, QP_H_LOWRANK = 1, QP_H_PTWP = 2 } qp_h_kind;
 typedef enum { QP_A_NONE = 0, QP_A_DENSE = 1, QP_A_CSR = 2 } qp_a_kind;
+/* Precision of the PCG matvec only.  Residuals, right-hand sides, the Jacobi
+ * diagonal, every inner product, the PCG vectors, the ratio test and the
+ * iterate stay float64 in all modes; reduced-precision solves replace the
+ * residual by its float64 value periodically and accept a solve only on the
+ * float64 residual. */
 typedef enum {
-  QP_PREC_FP64 = 0,   /* every operation in float64 */
-  QP_PREC_FP32 = 1,   /* PCG matvec values stored and accumulated in float32 */
-  QP_PREC_BF16 = 2    /* PCG matvec values stored in bfloat16, float32 accumulate */
+  QP_PREC_FP64 = 0,        /* every operation in float64 */
+  QP_PREC_FP32 = 1,        /* matvec values stored and accumulated in float32 */
+  QP_PREC_BF16 = 2,        /* matvec values stored in bfloat16, float32 accumulation */
+  QP_PREC_FP32_ACC64 = 3,  /* values stored in float32, float64 accumulation */
+  QP_PREC_BF16_ACC64 = 4   /* values stored in bfloat16, float64 accumulation */
 } qp_precision;
 
 /* Problem description (all pointers HOST, read only during qp_create). */
@@ -115,8 +122,9 @@ typedef struct {
   double tol;                /* default 1e-7 */
   int32_t maxit;             /* default 5000 */
   int32_t check_every;       /* iterations between host polls of the stop flag; default 8 */
-  int32_t rr_period;         /* mixed precision only: recompute r = rhs - K x in float64
-                              * and restart every rr_period iterations; default 50, 0 = off */
+  int32_t rr_period;         /* reduced precision only: replace r by the float64 residual
+                              * rhs - K x every rr_period iterations (search direction kept);
+                              * default 0 = only when the stop test fires */
 } pcg_options;
 
 typedef struct {
@@ -125,6 +133,10 @@ typedef struct {
   int32_t status;            /* qp_status of the solve */
   double rel_residual;       /* final ||rhs - K sol|| / ||rhs|| (float64 operator) */
   double rhs_norm;
+  int32_t escalated;         /* reduced precision only: 1 if the solve failed with the
+                              * reduced-precision operator (iteration cap, NaN, or lost
+                              * positive definiteness) and was redone in float64;
+                              * iterations then counts both attempts */
 } pcg_info;
 
 /* Algorithm 1 settings.  gamma of eq. (10); mu is divided by mu_div when the
@@ -158,6 +170,7 @@ typedef struct {
   int32_t iterations;        /* IPM iterations taken */
   int64_t total_cg_iters;
   int32_t cg_maxiter_hits;   /* Newton steps whose PCG stopped at maxit */
+  int32_t cg_escalations;    /* Newton steps redone with the float64 operator */
   double mu_final;
   double rnorm;              /* stacked residual norm at the returned point */
   double primal, dual, compl_; /* infeasibilities of Section 5.2 */

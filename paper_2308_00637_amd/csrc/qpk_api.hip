@@ -137,7 +137,7 @@ static inline uint16_t to_bf16(double v) {
 }
 
 static qp_status upload_lo(qp_handle h, void** p, const std::vector<double>& v) {
-  if (h->vk == VK_F32) {
+  if (h->vk == VK_F32 || h->vk == VK_F32X) {
     std::vector<float> f(v.size());
     for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
     float* d;
@@ -375,36 +375,53 @@ static qp_status read_back(qp_handle h) {
 
 // Step a5: Jacobi PCG (needs prepare()).  Also reports the true relative
 // residual ||rhs - K sol|| / ||rhs|| with the float64 operator.
-static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_options& o,
-                         pcg_info* info) {
-  CgArgs a = cg_args(h, rhs, sol, o);
-  HIPCHK(launch_cg_init(a, h->st));
-  const bool lo = h->vk != VK_F64;
-  const int check = std::max(1, o.check_every);
-  int it = 0;
-  bool done = false;
-  CHK(read_back(h));
-  done = h->hfl[F_DONE] != 0;
-  while (!done && it < o.maxit) {
-    const int chunk = std::min(check, o.maxit - it);
-    for (int c = 0; c < chunk; ++c, ++it) {
-      if (lo && o.rr_period > 0 && it > 0 && it % o.rr_period == 0) {
-        CHK(run_matvec(h, false, sol, h->tmp, h->fl + F_DONE, nullptr));
-        HIPCHK(launch_cg_restart(a, h->tmp, h->st));
-      }
-      CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT));
-      ProfScope ps(h, QP_PROF_CGVEC, true);
-      HIPCHK(launch_cg_update(a, h->st));
-      HIPCHK(launch_cg_pupdate(a, h->st));
-    }
-    HIPCHK(hipMemcpyAsync(h->hfl, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    done = h->hfl[F_DONE] != 0;
-  }
-  // true residual with the float64 operator
+static qp_status true_residual(qp_handle h, const double* rhs, const double* sol) {
   CHK(run_matvec(h, false, sol, h->tmp, nullptr, nullptr));
   HIPCHK(launch_sqdiff(rhs, h->tmp, h->N(), h->part + P_CHK * kGridMax, h->g_vec, h->st));
   HIPCHK(launch_finish_sum(h->part + P_CHK * kGridMax, h->g_vec, h->sc + S_RELRES, h->st));
+  return QP_OK;
+}
+
+static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_options& o,
+                         pcg_info* info, bool force64 = false) {
+  CgArgs a = cg_args(h, rhs, sol, o);
+  HIPCHK(launch_cg_init(a, h->st));
+  const bool lo = h->vk != VK_F64 && !force64;
+  const int check = std::max(1, o.check_every);
+  int it = 0;
+  CHK(read_back(h));
+  bool done = h->hfl[F_DONE] != 0;
+  const double rhsn = h->hsc[S_RHSNORM];
+  while (it < o.maxit) {
+    while (!done && it < o.maxit) {
+      const int chunk = std::min(check, o.maxit - it);
+      for (int c = 0; c < chunk; ++c, ++it) {
+        if (lo && o.rr_period > 0 && it > 0 && it % o.rr_period == 0) {
+          // residual replacement: r = rhs - K x with the float64 operator
+          CHK(run_matvec(h, false, sol, h->tmp, h->fl + F_DONE, nullptr));
+          HIPCHK(launch_cg_restart(a, h->tmp, 0, h->st));
+        }
+        CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT));
+        ProfScope ps(h, QP_PROF_CGVEC, true);
+        HIPCHK(launch_cg_update(a, h->st));
+        HIPCHK(launch_cg_pupdate(a, h->st));
+      }
+      HIPCHK(hipMemcpyAsync(h->hfl, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      done = h->hfl[F_DONE] != 0;
+    }
+    if (!lo || h->hfl[F_STATUS] != 1) break;
+    // Reduced-precision operator: the stop test saw the recurrence residual;
+    // accept only if the float64 residual passes too, else restart from it.
+    CHK(true_residual(h, rhs, sol));
+    CHK(read_back(h));
+    if (std::sqrt(h->hsc[S_RELRES]) <= o.tol * rhsn || h->hfl[F_ITERS] >= o.maxit) break;
+    HIPCHK(launch_cg_restart(a, h->tmp, 1, h->st));
+    it = h->hfl[F_ITERS];
+    done = false;
+  }
+  // true residual with the float64 operator
+  CHK(true_residual(h, rhs, sol));
   CHK(read_back(h));
   const int status = h->hfl[F_STATUS];
   pcg_info inf{};
@@ -416,6 +433,15 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
   if (status == QP_ERR_NUMERIC_CODE) inf.status = QP_ERR_NUMERIC;
   if (status == 0) inf.iterations = o.maxit;
   inf.rel_residual = inf.rhs_norm > 0.0 ? std::sqrt(h->hsc[S_RELRES]) / inf.rhs_norm : 0.0;
+  if (lo && (inf.status != QP_OK || !inf.converged || !(inf.rel_residual <= o.tol))) {
+    // the reduced-precision operator could not deliver this solve: redo it in float64
+    pcg_info again{};
+    const qp_status s2 = run_pcg(h, rhs, sol, o, &again, true);
+    again.iterations += inf.iterations;
+    again.escalated = 1;
+    if (info) *info = again;
+    return s2;
+  }
   if (info) *info = inf;
   if (inf.status == QP_ERR_NOT_SPD) {
     h->err = "PCG met a non-positive curvature p^T K p (H not convex, or the iterate is broken)";
@@ -487,7 +513,7 @@ void qp_default_pcg_options(pcg_options* o) {
   o->tol = 1e-7;
   o->maxit = 5000;
   o->check_every = 8;
-  o->rr_period = 50;
+  o->rr_period = 0;
 }
 
 void qp_default_ipm_options(ipm_options* o) {
@@ -601,7 +627,7 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   const int64_t n = d->n, m = d->m, me = d->me;
   auto bad = [&](const std::string& msg) { h->err = msg; return QP_ERR_ARG; };
   if (n <= 0 || m < 0 || me < 0 || me > 64) return bad("need n >= 1, m >= 0, 0 <= me <= 64");
-  if (d->precision < QP_PREC_FP64 || d->precision > QP_PREC_BF16) return bad("bad precision");
+  if (d->precision < QP_PREC_FP64 || d->precision > QP_PREC_BF16_ACC64) return bad("bad precision");
   if (!d->c) return bad("c is required");
   if (me > 0 && (!d->C || !d->b)) return bad("C and b are required when me > 0");
   if (m > 0 && (!d->lA || !d->uA)) return bad("lA and uA are required when m > 0");
@@ -609,7 +635,13 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   if (m == 0 && d->a_kind != QP_A_NONE && d->a_kind != QP_A_DENSE && d->a_kind != QP_A_CSR)
     return bad("bad a_kind");
   h->n = (int)n; h->m = (int)m; h->me = (int)me; h->h_kind = d->h_kind; h->prec = d->precision;
-  h->vk = d->precision == QP_PREC_FP32 ? VK_F32 : d->precision == QP_PREC_BF16 ? VK_BF16 : VK_F64;
+  switch (d->precision) {
+    case QP_PREC_FP32: h->vk = VK_F32; break;
+    case QP_PREC_BF16: h->vk = VK_BF16; break;
+    case QP_PREC_FP32_ACC64: h->vk = VK_F32X; break;
+    case QP_PREC_BF16_ACC64: h->vk = VK_BF16X; break;
+    default: h->vk = VK_F64; break;
+  }
   auto finite_all = [](const double* p, int64_t cnt) {
     for (int64_t i = 0; i < cnt; ++i) if (!std::isfinite(p[i])) return false;
     return true;
@@ -1123,6 +1155,7 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
     pcg_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
     info->total_cg_iters += pi.iterations;
     if (!pi.converged) info->cg_maxiter_hits++;
+    if (pi.escalated) info->cg_escalations++;
     CHK(run_recover(h, opt.gamma));
     VecArgs v = vec_args(h);
     HIPCHK(launch_update(v, h->dir, h->dir + h->n, h->ds_w, h->sc + S_ALPHA_X, 0.0, 0.0,
@@ -1245,7 +1278,7 @@ qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms) {
 qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
                             int64_t* dense_bytes, int64_t* row_nnz, int64_t* col_nnz) {
   if (!h) return QP_ERR_ARG;
-  const int64_t vb = h->vk == VK_F64 ? 8 : h->vk == VK_F32 ? 4 : 2;
+  const int64_t vb = h->vk == VK_F64 ? 8 : (h->vk == VK_F32 || h->vk == VK_F32X) ? 4 : 2;
   // bytes of the structures the PCG matvec streams (values, column indices, row pointers)
   auto ck_bytes = [&](const qp_handle_s::Chunked& k) {
     return k.nnz * (vb + 2) + 4 * (int64_t)k.nchunk * (k.nrows + 1);

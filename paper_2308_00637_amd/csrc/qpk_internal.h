@@ -18,7 +18,8 @@ constexpr int kGridMax = 2048;   // cap on blocks of grid-stride kernels (= part
 constexpr int QP_ERR_NOT_SPD_CODE = -4;   // mirrors qp_status in qpk.h
 constexpr int QP_ERR_NUMERIC_CODE = -5;
 
-enum ValKind : int { VK_F64 = 0, VK_F32 = 1, VK_BF16 = 2 };
+// Stored value type and accumulation type of the PCG matvec passes.
+enum ValKind : int { VK_F64 = 0, VK_F32 = 1, VK_BF16 = 2, VK_F32X = 3, VK_BF16X = 4 };
 
 // Row-side pass modes
 enum RowMode : int {
@@ -251,7 +252,7 @@ struct CgArgs {
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t st);
 hipError_t launch_cg_update(const CgArgs& a, hipStream_t st);
 hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st);
-hipError_t launch_cg_restart(const CgArgs& a, const double* kx, hipStream_t st);
+hipError_t launch_cg_restart(const CgArgs& a, const double* kx, int resume, hipStream_t st);
 
 // Backward: gradient outputs from the adjoint solution u (K-vector layout).
 hipError_t launch_grad_out(int n, int m, int me, const double* u, const double* lA,

@@ -22,6 +22,8 @@ template <int VK> struct VT;
 template <> struct VT<VK_F64> { using T = double;   using Acc = double; };
 template <> struct VT<VK_F32> { using T = float;    using Acc = float; };
 template <> struct VT<VK_BF16> { using T = uint16_t; using Acc = float; };
+template <> struct VT<VK_F32X> { using T = float;    using Acc = double; };
+template <> struct VT<VK_BF16X> { using T = uint16_t; using Acc = double; };
 
 __device__ __forceinline__ double ldv(const double* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
@@ -874,10 +876,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(CgArgs a) {
     a.p[i] = a.z[i] + beta * a.p[i];
 }
 
-// Residual replacement for the reduced-precision operator: r = rhs - K x with
-// the float64 operator, then restart the recurrence from z = r / diag.
-__global__ __launch_bounds__(kBlock) void k_cg_restart(CgArgs a, const double* kx) {
-  if (a.fl[F_DONE]) return;
+// Residual replacement for the reduced-precision operator (the reliable-update
+// form of van der Vorst and Ye, 2000): r = rhs - K x with the float64 operator,
+// z = r / diag, and the search direction p is kept, so the Krylov process goes
+// on; the next alpha uses the replaced r . z.  On a resume (the recurrence
+// residual met the tolerance but the float64 one did not) the replaced residual
+// is unrelated to p, so the search restarts from p = z.
+__global__ __launch_bounds__(kBlock) void k_cg_restart(CgArgs a, const double* kx, int resume) {
+  if (!resume && a.fl[F_DONE]) return;
   const int k = a.fl[F_CNT] + 1;  // the iteration about to run
   double rz = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock) {
@@ -885,11 +891,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_restart(CgArgs a, const double* k
     const double z = r / a.jdiag[i];
     a.r[i] = r;
     a.z[i] = z;
-    a.p[i] = z;
+    if (resume) a.p[i] = z;
     rz += r * z;
   }
   rz = block_sum(rz);
   if (threadIdx.x == 0) a.part[((k & 1) ? P_RZ1 : P_RZ0) * kGridMax + blockIdx.x] = rz;
+}
+
+// Re-arms the iteration after a resume (the stop flag was set on the
+// recurrence residual, but the float64 residual is not yet small enough).
+__global__ void k_cg_rearm(int* fl) {
+  if (threadIdx.x == 0) {
+    fl[F_DONE] = 0;
+    fl[F_STATUS] = 0;
+  }
 }
 
 // Squared distance partials (true residual ||rhs - K x||^2).
@@ -992,6 +1007,8 @@ hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid,
   if (mode == R_MATVEC) {
     if (vk == VK_F32) return rowpass_lpr<R_MATVEC, VK_F32>(lpr, a, grid, st);
     if (vk == VK_BF16) return rowpass_lpr<R_MATVEC, VK_BF16>(lpr, a, grid, st);
+    if (vk == VK_F32X) return rowpass_lpr<R_MATVEC, VK_F32X>(lpr, a, grid, st);
+    if (vk == VK_BF16X) return rowpass_lpr<R_MATVEC, VK_BF16X>(lpr, a, grid, st);
     return rowpass_lpr<R_MATVEC, VK_F64>(lpr, a, grid, st);
   }
   switch (mode) {
@@ -1008,6 +1025,8 @@ hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid,
   if (mode == X_MATVEC) {
     if (vk == VK_F32) return colpass_lpr<X_MATVEC, VK_F32>(lpr, a, grid, st);
     if (vk == VK_BF16) return colpass_lpr<X_MATVEC, VK_BF16>(lpr, a, grid, st);
+    if (vk == VK_F32X) return colpass_lpr<X_MATVEC, VK_F32X>(lpr, a, grid, st);
+    if (vk == VK_BF16X) return colpass_lpr<X_MATVEC, VK_BF16X>(lpr, a, grid, st);
     return colpass_lpr<X_MATVEC, VK_F64>(lpr, a, grid, st);
   }
   switch (mode) {
@@ -1039,6 +1058,8 @@ static hipError_t chunked_vk(int vk, int lpr, const ChunkArgs& c, const RowArgs&
                              const ColArgs& ca, int nwork, hipStream_t st) {
   if (vk == VK_F32) return chunked_lpr<EPI, VK_F32>(lpr, c, ra, ca, nwork, st);
   if (vk == VK_BF16) return chunked_lpr<EPI, VK_BF16>(lpr, c, ra, ca, nwork, st);
+  if (vk == VK_F32X) return chunked_lpr<EPI, VK_F32X>(lpr, c, ra, ca, nwork, st);
+  if (vk == VK_BF16X) return chunked_lpr<EPI, VK_BF16X>(lpr, c, ra, ca, nwork, st);
   return chunked_lpr<EPI, VK_F64>(lpr, c, ra, ca, nwork, st);
 }
 
@@ -1067,6 +1088,12 @@ static hipError_t set_attr_lpr() {
 hipError_t chunked_set_attributes() {
   hipError_t e = hipSuccess;
   auto chain = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chain(set_attr_lpr<CE_PARTIAL, VK_F32X>());
+  chain(set_attr_lpr<CE_PARTIAL, VK_BF16X>());
+  chain(set_attr_lpr<CE_ROW, VK_F32X>());
+  chain(set_attr_lpr<CE_ROW, VK_BF16X>());
+  chain(set_attr_lpr<CE_COL, VK_F32X>());
+  chain(set_attr_lpr<CE_COL, VK_BF16X>());
   chain(set_attr_lpr<CE_PARTIAL, VK_F64>());
   chain(set_attr_lpr<CE_PARTIAL, VK_F32>());
   chain(set_attr_lpr<CE_PARTIAL, VK_BF16>());
@@ -1092,6 +1119,8 @@ hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int 
 hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st) {
   if (vk == VK_F32) k_ts_reduce<VK_F32><<<grid, kBlock, 0, st>>>(a);
   else if (vk == VK_BF16) k_ts_reduce<VK_BF16><<<grid, kBlock, 0, st>>>(a);
+  else if (vk == VK_F32X) k_ts_reduce<VK_F32X><<<grid, kBlock, 0, st>>>(a);
+  else if (vk == VK_BF16X) k_ts_reduce<VK_BF16X><<<grid, kBlock, 0, st>>>(a);
   else k_ts_reduce<VK_F64><<<grid, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
@@ -1150,8 +1179,9 @@ hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st) {
   k_cg_pupdate<<<a.g_vec, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
-hipError_t launch_cg_restart(const CgArgs& a, const double* kx, hipStream_t st) {
-  k_cg_restart<<<a.g_vec, kBlock, 0, st>>>(a, kx);
+hipError_t launch_cg_restart(const CgArgs& a, const double* kx, int resume, hipStream_t st) {
+  k_cg_restart<<<a.g_vec, kBlock, 0, st>>>(a, kx, resume);
+  if (resume) k_cg_rearm<<<1, 64, 0, st>>>(a.fl);
   return hipGetLastError();
 }
 hipError_t launch_grad_out(int n, int m, int me, const double* u, const double* lA,

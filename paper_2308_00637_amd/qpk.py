@@ -28,7 +28,7 @@ QP_ERR_UNSUPPORTED = -7
 
 H_DENSE, H_LOWRANK, H_PTWP = 0, 1, 2
 A_NONE, A_DENSE, A_CSR = 0, 1, 2
-PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp32x64": 3, "bf16x64": 4}
 
 _dp = C.POINTER(C.c_double)
 _i64p = C.POINTER(C.c_int64)
@@ -53,7 +53,7 @@ class PcgOptions(C.Structure):
 
 class PcgInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
-                ("rel_residual", C.c_double), ("rhs_norm", C.c_double)]
+                ("rel_residual", C.c_double), ("rhs_norm", C.c_double), ("escalated", C.c_int32)]
 
 
 class IpmOptions(C.Structure):
@@ -70,7 +70,7 @@ class IpmOptions(C.Structure):
 class IpmInfo(C.Structure):
     _fields_ = [
         ("result", C.c_int32), ("iterations", C.c_int32), ("total_cg_iters", C.c_int64),
-        ("cg_maxiter_hits", C.c_int32), ("mu_final", C.c_double), ("rnorm", C.c_double),
+        ("cg_maxiter_hits", C.c_int32), ("cg_escalations", C.c_int32), ("mu_final", C.c_double), ("rnorm", C.c_double),
         ("primal", C.c_double), ("dual", C.c_double), ("compl_", C.c_double),
         ("objective", C.c_double), ("time_ms", C.c_double), ("pcg_time_ms", C.c_double),
     ]
