@@ -262,6 +262,16 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c,
                       double* grad_lA, double* grad_uA, double* grad_b,
                       double* grad_w, const pcg_options* o, pcg_info* info);
 
+/* Replace problem data in place (DEVICE pointers, NULL = keep): the linear
+ * term c (n), the row bounds lA, uA (m, +-INFINITY allowed, with the same
+ * finite/infinite pattern as at creation), the equality right-hand side b
+ * (me), and for QP_H_PTWP the voxel weights w (p_rows, positive).  The
+ * derived constants (diag(H), c - P^T W d) are recomputed on the device.
+ * Invalidates any completed solve (qp_backward then needs a new ipm_solve).
+ * For the differentiable wrapper, which changes only these parameters. */
+qp_status qp_update_data(qp_handle h, const double* c, const double* lA, const double* uA,
+                         const double* b, const double* w);
+
 /* Kernel timing with HIP events on the handle's stream (instrumentation, not
  * part of the method).  qp_profile_begin(h, max_launches) pre-creates events for
  * up to max_launches timed launches per category; until qp_profile_end every

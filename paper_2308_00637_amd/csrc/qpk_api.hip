@@ -35,6 +35,7 @@ struct qp_handle_s {
   double *wd = nullptr, *h0 = nullptr, *Cm = nullptr, *b = nullptr, *c = nullptr, *c_eff = nullptr;
   double *lA = nullptr, *uA = nullptr, *lx = nullptr, *ux = nullptr, *pw = nullptr, *pd = nullptr;
   double* diagH = nullptr;
+  double* diagH0 = nullptr;  // dense-H diagonal and h0: the part of diag(H) not derived on the device
   bool has_xs = false, has_ts = false;
   // iterate
   double *x = nullptr, *lam = nullptr, *s = nullptr;
@@ -491,6 +492,27 @@ static qp_status run_objective(qp_handle h, double* out) {
   return QP_OK;
 }
 
+// Constant parts: diag(H) = diagH0 + diag(P^T W P) + sum_l wd_l U_jl^2 and
+// c_eff = c - P^T W d.
+static qp_status derive_constants(qp_handle h) {
+  if (h->p_rows > 0 || h->k > 0) {
+    ColArgs c = col_args(h, false);
+    c.use_hx = 0; c.use_at = 0; c.use_pt = h->p_rows > 0;
+    c.v = h->diagH0; c.y = h->diagH;
+    HIPCHK(launch_colpass(X_DIAGH, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  } else {
+    HIPCHK(launch_copy(h->diagH0, h->diagH, h->n, 1.0, h->st));
+  }
+  if (h->p_rows > 0 && h->pd) {
+    ColArgs c = col_args(h, false);
+    c.use_hx = 0; c.use_at = 0; c.use_pt = 1; c.src_pt = h->pd; c.c = h->c; c.y = h->c_eff;
+    HIPCHK(launch_colpass(X_CEFF, VK_F64, h->lpr_x, c, h->g_x, h->st));
+  } else {
+    HIPCHK(launch_copy(h->c, h->c_eff, h->n, 1.0, h->st));
+  }
+  return QP_OK;
+}
+
 static qp_status run_init_state(qp_handle h, double mu) {
   h->mu = mu;
   VecArgs v = vec_args(h);
@@ -869,7 +891,7 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   } else {
     CHK(dalloc_t(h, &h->pw, 1));
   }
-  CHK(upload(h, &h->diagH, diagH.data(), n));
+  CHK(dalloc_t(h, &h->diagH, n));
 
   const int64_t N = h->N();
   CHK(dalloc_t(h, &h->x, n));
@@ -918,20 +940,8 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
     }
   }
 
-  // Constant parts: diag(H) += diag(P^T W P) + sum_l wd_l U_jl^2; c_eff = c - P^T W d.
-  if (p_rows > 0 || k > 0) {
-    ColArgs c = col_args(h, false);
-    c.use_hx = 0; c.use_at = 0; c.use_pt = p_rows > 0;
-    c.v = h->diagH; c.y = h->diagH;
-    HIPCHK(launch_colpass(X_DIAGH, VK_F64, h->lpr_x, c, h->g_x, h->st));
-  }
-  if (p_rows > 0 && h->pd) {
-    ColArgs c = col_args(h, false);
-    c.use_hx = 0; c.use_at = 0; c.use_pt = 1; c.src_pt = h->pd; c.c = h->c; c.y = h->c_eff;
-    HIPCHK(launch_colpass(X_CEFF, VK_F64, h->lpr_x, c, h->g_x, h->st));
-  } else {
-    HIPCHK(launch_copy(h->c, h->c_eff, n, 1.0, h->st));
-  }
+  CHK(upload(h, &h->diagH0, diagH.data(), n));
+  CHK(derive_constants(h));
   CHK(run_init_state(h, 1.0));
   HIPCHK(hipStreamSynchronize(h->st));
   return QP_OK;
@@ -1237,6 +1247,25 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c, double*
     a.r0 = 0; a.r1 = h->p_rows; a.v = usol; a.v2 = h->x; a.gw = grad_w;
     HIPCHK(launch_rowpass(R_GRADW, VK_F64, h->lpr_r, a, h->g_r, h->st));
   }
+  HIPCHK(hipStreamSynchronize(h->st));
+  return QP_OK;
+}
+
+qp_status qp_update_data(qp_handle h, const double* c, const double* lA, const double* uA,
+                         const double* b, const double* w) {
+  if (!h) return QP_ERR_ARG;
+  if (w && h->p_rows == 0) {
+    h->err = "weights apply to a P^T W P Hessian only";
+    return QP_ERR_ARG;
+  }
+  if (c) HIPCHK(hipMemcpyAsync(h->c, c, sizeof(double) * h->n, hipMemcpyDeviceToDevice, h->st));
+  if (lA && h->m) HIPCHK(hipMemcpyAsync(h->lA, lA, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->st));
+  if (uA && h->m) HIPCHK(hipMemcpyAsync(h->uA, uA, sizeof(double) * h->m, hipMemcpyDeviceToDevice, h->st));
+  if (b && h->me) HIPCHK(hipMemcpyAsync(h->b, b, sizeof(double) * h->me, hipMemcpyDeviceToDevice, h->st));
+  if (w) HIPCHK(hipMemcpyAsync(h->pw, w, sizeof(double) * h->p_rows, hipMemcpyDeviceToDevice, h->st));
+  CHK(derive_constants(h));
+  h->res_valid = h->sys_valid = false;
+  h->solved = false;
   HIPCHK(hipStreamSynchronize(h->st));
   return QP_OK;
 }

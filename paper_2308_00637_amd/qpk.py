@@ -81,7 +81,7 @@ EXPORTS = [
     "qp_create", "qp_destroy", "qp_set_stream", "qp_sizes", "qp_set_state", "qp_get_state",
     "qp_init_state", "qp_residuals", "qp_newton_rhs", "qp_kkt_matvec", "kkt_pcg_solve",
     "qp_newton_direction", "qp_step_lengths", "qp_take_step", "ipm_solve", "qp_backward",
-    "qp_profile_begin", "qp_profile_end", "qp_operator_bytes",
+    "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_update_data",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "cgvec")
 
@@ -116,6 +116,7 @@ def _load():
         "qp_profile_begin": (C.c_int, [vp, C.c_int32]),
         "qp_profile_end": (C.c_int, [vp, _i64p, _dp]),
         "qp_operator_bytes": (C.c_int, [vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
+        "qp_update_data": (C.c_int, [vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -341,6 +342,9 @@ class QP:
             k = info.iterations
             logs = {key: v[:k].copy() for key, v in logs.items()}
         return dict(x=x, lam=lam, s=s, info=info, log=logs)
+
+    def update_data(self, c=None, lA=None, uA=None, b=None, w=None):
+        self._check(LIB.qp_update_data(self.h, _dev(c), _dev(lA), _dev(uA), _dev(b), _dev(w)))
 
     def profile_begin(self, max_launches: int):
         self._check(LIB.qp_profile_begin(self.h, int(max_launches)))

@@ -1,0 +1,87 @@
+"""qp_backward (adjoint PCG on the doubly augmented matrix) against the
+oracle's adjoint, which solves the transposed unreduced Jacobian of eq. (7)
+by dense LU at the same point.  The oracle adjoint itself is pinned by central
+differences of centered solves (tests/test_oracle_pins.py)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import from_masked, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def small_case():
+    spec = W.rt_qp(4, 60, 8, 0.3, 8, maxdose=0.3)
+    spec.c = np.random.default_rng(4).standard_normal(spec.n) * 0.5
+    return spec
+
+
+def adjoint_case():
+    """20,000 voxels x 2,000 beamlets, 1,000 max-dose rows; x_ref ~ U(0, 1)."""
+    spec = W.rt_small(4)
+    return spec
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("case", ["small", "rt_20000x2000"])
+def test_backward_matches_oracle_adjoint(case):
+    from paper_2308_00637_amd.qpk import QP, default_pcg_options
+    spec = small_case() if case == "small" else adjoint_case()
+    prob = O.from_spec(spec)
+    xref = np.random.default_rng(5).uniform(0, 1, spec.n)
+    qp = QP(spec)
+    out = qp.solve()
+    info = out["info"]
+    assert info.result == 0
+    x = out["x"].cpu().numpy()
+    gx = 2.0 * (x - xref)
+    g, pinfo = qp.backward(dev(gx), opts=default_pcg_options(tol=1e-11, maxit=50000))
+    print(f"{case}: ipm={info.iterations} adjoint pcg iters={pinfo.iterations} "
+          f"relres={pinfo.rel_residual:.2e}", flush=True)
+    assert pinfo.converged == 1
+    st = from_masked(prob, x, out["lam"].cpu().numpy(), out["s"].cpu().numpy())
+    ref = O.adjoint_gradients(prob, st, info.mu_final, gx, P=spec.P, w=spec.w, d=spec.d)
+    for key, ok in (("c", "c"), ("uA", "u"), ("w", "w")):
+        e = rel(g[key].cpu().numpy(), ref[ok])
+        print(f"  d/d{key}: rel err {e:.2e} (norm {np.linalg.norm(ref[ok]):.3e})", flush=True)
+        assert e <= 1e-6, key
+    assert np.all(g["lA"].cpu().numpy() == 0.0)   # no row has a finite lower side
+
+
+def test_backward_before_solve_is_a_state_error():
+    from paper_2308_00637_amd.qpk import QP, QPError, QP_ERR_STATE
+    spec = small_case()
+    qp = QP(spec)
+    with pytest.raises(QPError) as e:
+        qp.backward(dev(np.ones(spec.n)))
+    assert e.value.status == QP_ERR_STATE
+
+
+def test_autograd_function():
+    from paper_2308_00637_amd.autograd import qp_layer
+    from paper_2308_00637_amd.qpk import QP
+    spec = small_case()
+    prob = O.from_spec(spec)
+    qp = QP(spec)
+    c = dev(spec.c).requires_grad_(True)
+    uA = dev(spec.uA).requires_grad_(True)
+    w = dev(spec.w).requires_grad_(True)
+    xref = dev(np.random.default_rng(5).uniform(0, 1, spec.n))
+    x = qp_layer(qp, c=c, uA=uA, w=w)
+    loss = ((x - xref) ** 2).sum()
+    loss.backward()
+    _, lam, s, mu = qp.get_state()
+    st = from_masked(prob, x.detach().cpu().numpy(), lam.cpu().numpy(), s.cpu().numpy())
+    ref = O.adjoint_gradients(prob, st, mu, 2 * (st.x - xref.cpu().numpy()), P=spec.P, w=spec.w, d=spec.d)
+    assert rel(c.grad.cpu().numpy(), ref["c"]) <= 1e-6
+    assert rel(uA.grad.cpu().numpy(), ref["u"]) <= 1e-6
+    assert rel(w.grad.cpu().numpy(), ref["w"]) <= 1e-6
+    # a second forward with changed data reuses the handle
+    x2 = qp_layer(qp, c=(c.detach() * 1.01))
+    assert torch.isfinite(x2).all() and not torch.equal(x2, x.detach())
