@@ -262,6 +262,28 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c,
                       double* grad_lA, double* grad_uA, double* grad_b,
                       double* grad_w, const pcg_options* o, pcg_info* info);
 
+/* ---- Batches of independent QPs (one persistent launch) ----
+ * qp_batch_create copies `count` problem descriptions (HOST pointers, as for
+ * qp_create) into one device pool.  Supported per instance: H dense or low
+ * rank, A dense (or m = 0), any row and variable bounds, no equality rows
+ * (me = 0); precision QP_PREC_FP64 or QP_PREC_FP32 (operator storage, same
+ * for all instances; vectors and reductions stay float64).  Other inputs give
+ * QP_ERR_UNSUPPORTED; invalid data QP_ERR_ARG (see qp_batch_last_error(NULL)).
+ * ipm_solve_batch runs Algorithm 1 for every instance in one kernel launch:
+ * `workgroups` (<= 0: 512) workgroups of 1024 threads take instances from a
+ * queue, largest first, and each solves its instances start to finish (same
+ * steps, readings and defaults as ipm_solve; per-iteration logs are not
+ * kept).  infos: HOST array of `count`, each time_ms is the whole launch.
+ * Returns QP_ERR_NOT_SPD / QP_ERR_NUMERIC if an instance stopped on one
+ * (the others are still solved).  qp_batch_get_solution copies instance i's
+ * iterate (DEVICE pointers, layouts as for a single handle with me = 0). */
+typedef struct qp_batch_s* qp_batch;
+qp_status qp_batch_create(const qp_desc* descs, int32_t count, void* stream, qp_batch* out);
+void qp_batch_destroy(qp_batch b);
+qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, ipm_info* infos);
+qp_status qp_batch_get_solution(qp_batch b, int32_t i, double* x, double* lam, double* s);
+const char* qp_batch_last_error(qp_batch b);
+
 /* Replace problem data in place (DEVICE pointers, NULL = keep): the linear
  * term c (n), the row bounds lA, uA (m, +-INFINITY allowed, with the same
  * finite/infinite pattern as at creation), the equality right-hand side b

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpk.so")
-SOURCES = ["qpk_kernels.hip", "qpk_api.hip"]
+SOURCES = ["qpk_kernels.hip", "qpk_api.hip", "qpk_batch.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

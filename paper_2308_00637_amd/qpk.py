@@ -82,6 +82,8 @@ EXPORTS = [
     "qp_init_state", "qp_residuals", "qp_newton_rhs", "qp_kkt_matvec", "kkt_pcg_solve",
     "qp_newton_direction", "qp_step_lengths", "qp_take_step", "ipm_solve", "qp_backward",
     "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_update_data",
+    "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
+    "qp_batch_last_error",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "cgvec")
 
@@ -117,6 +119,11 @@ def _load():
         "qp_profile_end": (C.c_int, [vp, _i64p, _dp]),
         "qp_operator_bytes": (C.c_int, [vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
         "qp_update_data": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "qp_batch_create": (C.c_int, [C.POINTER(QpDesc), C.c_int32, vp, C.POINTER(vp)]),
+        "qp_batch_destroy": (None, [vp]),
+        "ipm_solve_batch": (C.c_int, [vp, C.POINTER(IpmOptions), C.c_int32, C.POINTER(IpmInfo)]),
+        "qp_batch_get_solution": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
+        "qp_batch_last_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -181,60 +188,66 @@ class Sizes:
     res: int
 
 
+def make_desc(spec, precision: str = "fp64"):
+    """QpDesc for a workload description; returns (desc, arrays it points into)."""
+    f64 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    keep = []
+
+    def hold(a):
+        keep.append(a)
+        return a
+
+    d = QpDesc()
+    n = int(spec.n)
+    d.n, d.m, d.me = n, int(spec.m), int(spec.me)
+    d.precision = PREC[precision]
+    d.c = _ptr(hold(f64(spec.c)), C.c_double)
+    if spec.h_kind == "dense":
+        d.h_kind = H_DENSE
+        d.H = _ptr(hold(f64(spec.H)), C.c_double)
+    elif spec.h_kind == "lowrank":
+        d.h_kind = H_LOWRANK
+        d.k = int(spec.U.shape[1])
+        d.h0 = _ptr(hold(f64(spec.h0)), C.c_double)
+        d.U = _ptr(hold(f64(spec.U)), C.c_double)
+        d.wd = _ptr(hold(f64(spec.wd)), C.c_double)
+    elif spec.h_kind == "ptwp":
+        d.h_kind = H_PTWP
+        P = spec.P
+        d.p_rows = int(P.shape[0])
+        d.p_rowptr = _ptr(hold(np.ascontiguousarray(P.indptr, dtype=np.int64)), C.c_int64)
+        d.p_col = _ptr(hold(np.ascontiguousarray(P.indices, dtype=np.int32)), C.c_int32)
+        d.p_val = _ptr(hold(f64(P.data)), C.c_double)
+        d.p_w = _ptr(hold(f64(spec.w)), C.c_double)
+        d.p_d = _ptr(hold(f64(spec.d)), C.c_double)
+    else:
+        raise ValueError(spec.h_kind)
+    if spec.A is None:
+        d.a_kind = A_NONE
+    elif hasattr(spec.A, "indptr"):
+        d.a_kind = A_CSR
+        d.a_rowptr = _ptr(hold(np.ascontiguousarray(spec.A.indptr, dtype=np.int64)), C.c_int64)
+        d.a_col = _ptr(hold(np.ascontiguousarray(spec.A.indices, dtype=np.int32)), C.c_int32)
+        d.a_val = _ptr(hold(f64(spec.A.data)), C.c_double)
+    else:
+        d.a_kind = A_DENSE
+        d.A = _ptr(hold(f64(spec.A)), C.c_double)
+    if spec.A is not None:
+        d.lA = _ptr(hold(f64(spec.lA)), C.c_double)
+        d.uA = _ptr(hold(f64(spec.uA)), C.c_double)
+    if spec.C is not None:
+        d.C = _ptr(hold(f64(spec.C)), C.c_double)
+        d.b = _ptr(hold(f64(spec.b)), C.c_double)
+    d.lx = _ptr(hold(f64(spec.lx)), C.c_double)
+    d.ux = _ptr(hold(f64(spec.ux)), C.c_double)
+    return d, keep
+
+
 class QP:
     """Owns one qp_handle built from a workload description (`QPSpec`)."""
 
     def __init__(self, spec, precision: str = "fp64"):
-        f64 = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
-        keep = []
-
-        def hold(a):
-            keep.append(a)
-            return a
-
-        d = QpDesc()
-        n = int(spec.n)
-        d.n, d.m, d.me = n, int(spec.m), int(spec.me)
-        d.precision = PREC[precision]
-        d.c = _ptr(hold(f64(spec.c)), C.c_double)
-        if spec.h_kind == "dense":
-            d.h_kind = H_DENSE
-            d.H = _ptr(hold(f64(spec.H)), C.c_double)
-        elif spec.h_kind == "lowrank":
-            d.h_kind = H_LOWRANK
-            d.k = int(spec.U.shape[1])
-            d.h0 = _ptr(hold(f64(spec.h0)), C.c_double)
-            d.U = _ptr(hold(f64(spec.U)), C.c_double)
-            d.wd = _ptr(hold(f64(spec.wd)), C.c_double)
-        elif spec.h_kind == "ptwp":
-            d.h_kind = H_PTWP
-            P = spec.P
-            d.p_rows = int(P.shape[0])
-            d.p_rowptr = _ptr(hold(np.ascontiguousarray(P.indptr, dtype=np.int64)), C.c_int64)
-            d.p_col = _ptr(hold(np.ascontiguousarray(P.indices, dtype=np.int32)), C.c_int32)
-            d.p_val = _ptr(hold(f64(P.data)), C.c_double)
-            d.p_w = _ptr(hold(f64(spec.w)), C.c_double)
-            d.p_d = _ptr(hold(f64(spec.d)), C.c_double)
-        else:
-            raise ValueError(spec.h_kind)
-        if spec.A is None:
-            d.a_kind = A_NONE
-        elif hasattr(spec.A, "indptr"):
-            d.a_kind = A_CSR
-            d.a_rowptr = _ptr(hold(np.ascontiguousarray(spec.A.indptr, dtype=np.int64)), C.c_int64)
-            d.a_col = _ptr(hold(np.ascontiguousarray(spec.A.indices, dtype=np.int32)), C.c_int32)
-            d.a_val = _ptr(hold(f64(spec.A.data)), C.c_double)
-        else:
-            d.a_kind = A_DENSE
-            d.A = _ptr(hold(f64(spec.A)), C.c_double)
-        if spec.A is not None:
-            d.lA = _ptr(hold(f64(spec.lA)), C.c_double)
-            d.uA = _ptr(hold(f64(spec.uA)), C.c_double)
-        if spec.C is not None:
-            d.C = _ptr(hold(f64(spec.C)), C.c_double)
-            d.b = _ptr(hold(f64(spec.b)), C.c_double)
-        d.lx = _ptr(hold(f64(spec.lx)), C.c_double)
-        d.ux = _ptr(hold(f64(spec.ux)), C.c_double)
+        d, keep = make_desc(spec, precision)
         h = C.c_void_p()
         st = LIB.qp_create(C.byref(d), _stream(), C.byref(h))
         if st != QP_OK:
@@ -376,3 +389,49 @@ class QP:
                                     _dev(out["uA"]), _dev(out["b"]), _dev(out["w"]),
                                     C.byref(opts) if opts is not None else None, C.byref(info)))
         return out, info
+
+
+class QPBatch:
+    """Owns one qp_batch: many independent dense QPs solved in one launch."""
+
+    def __init__(self, specs, precision: str = "fp64"):
+        descs = (QpDesc * len(specs))()
+        self._keep = []
+        for i, sp in enumerate(specs):
+            d, keep = make_desc(sp, precision)
+            descs[i] = d
+            self._keep.append(keep)
+        h = C.c_void_p()
+        st = LIB.qp_batch_create(descs, len(specs), _stream(), C.byref(h))
+        if st != QP_OK:
+            raise QPError(st, LIB.qp_batch_last_error(None).decode())
+        self.h = h
+        self.specs = list(specs)
+        self._keep = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            LIB.qp_batch_destroy(h)
+            self.h = None
+
+    def solve(self, opts: Optional[IpmOptions] = None, workgroups: int = 0):
+        if opts is None:
+            opts = default_ipm_options()
+        infos = (IpmInfo * len(self.specs))()
+        st = LIB.ipm_solve_batch(self.h, C.byref(opts), int(workgroups), infos)
+        if st not in (QP_OK, QP_ERR_NOT_SPD, QP_ERR_NUMERIC):
+            raise QPError(st, LIB.qp_batch_last_error(self.h).decode())
+        return list(infos), st
+
+    def solution(self, i):
+        import torch
+        sp = self.specs[i]
+        n, m = int(sp.n), int(sp.m)
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        lam = torch.empty(2 * m + 2 * n, dtype=torch.float64, device="cuda")
+        s = torch.empty(2 * m + 2 * n, dtype=torch.float64, device="cuda")
+        st = LIB.qp_batch_get_solution(self.h, int(i), _dev(x), _dev(lam), _dev(s))
+        if st != QP_OK:
+            raise QPError(st, LIB.qp_batch_last_error(self.h).decode())
+        return x, lam, s

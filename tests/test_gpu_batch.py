@@ -1,0 +1,90 @@
+"""Batched persistent solve (ipm_solve_batch): every instance of an uneven
+batch against the CPU oracle, in float64 and float32 operator storage."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import from_masked
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def uneven_batch(count=24, seed=7, nmin=20, nmax=160, round_f32=False):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        if i % 3 == 0:
+            sp = W.random_bounded_qp(100 + i, n, int(rng.integers(0, 2 * n)), 0, max(2, n // 3),
+                                     h_kind="lowrank" if i % 2 else "dense")
+            sp.A = None if sp.A.shape[0] == 0 else np.asarray(sp.A)
+            if sp.A is None:
+                sp.lA = sp.uA = None
+        else:
+            m = int(rng.integers(n, 2 * n + 1))
+            sp = W.dense_qp(rng, n, m, n // 2, round_f32=round_f32, name=f"dense{i}")
+        specs.append(sp)
+    return specs
+
+
+def to_f32(sp):
+    """Round every operator and vector of a spec to float32 values, so that
+    float32 storage holds the problem exactly."""
+    r = lambda a: None if a is None else np.asarray(a, dtype=np.float32).astype(np.float64)
+    for f in ("c", "H", "h0", "U", "wd", "A", "lA", "uA", "lx", "ux"):
+        v = getattr(sp, f)
+        if v is not None:
+            setattr(sp, f, r(v))
+    return sp
+
+
+def check(specs, infos, qb, tol_obj=1e-6):
+    for i, sp in enumerate(specs):
+        prob = O.from_spec(sp)
+        ref = O.solve(prob)
+        f = infos[i]
+        x, lam, s = qb.solution(i)
+        st = from_masked(prob, x.cpu().numpy(), lam.cpu().numpy(), s.cpu().numpy())
+        kkt = O.stacked_norm(O.residuals(prob, st, f.mu_final))
+        err = abs(f.objective - ref.objective) / max(1.0, abs(ref.objective))
+        assert f.result == 0 and ref.status == "converged", (i, f.result)
+        assert err <= tol_obj, (i, err)
+        # the residual at convergence is a cancellation of O(1..100) terms, so
+        # the device's and the oracle's evaluations agree to rounding in absolute terms
+        assert kkt <= 1e-6 and abs(kkt - f.rnorm) <= 1e-10, (i, kkt, f.rnorm)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_matches_oracle_per_instance(prec):
+    from paper_2308_00637_amd.qpk import QPBatch
+    specs = uneven_batch()
+    if prec == "fp32":
+        specs = [to_f32(sp) for sp in specs]
+    qb = QPBatch(specs, precision=prec)
+    infos, st = qb.solve()
+    print(f"batch {prec}: {len(specs)} instances in {infos[0].time_ms:.1f} ms, "
+          f"ipm iters {[f.iterations for f in infos]}", flush=True)
+    assert st == 0
+    check(specs, infos, qb)
+
+
+def test_batch_of_one_tiny_dense_matches_oracle_and_single_path():
+    """The 200-variable case: one persistent launch vs the multi-kernel path."""
+    from paper_2308_00637_amd.qpk import QP, QPBatch
+    spec = W.tiny_dense(0)
+    qb = QPBatch([spec])
+    infos, st = qb.solve()
+    out = QP(spec).solve()
+    print(f"tiny_dense: batch {infos[0].time_ms:.1f} ms ({infos[0].iterations} ipm, "
+          f"{infos[0].total_cg_iters} cg) vs multi-kernel {out['info'].time_ms:.1f} ms "
+          f"({out['info'].iterations} ipm, {out['info'].total_cg_iters} cg)", flush=True)
+    check([spec], infos, qb)
+
+
+def test_batch_rejects_unsupported_inputs():
+    from paper_2308_00637_amd.qpk import QPBatch, QPError, QP_ERR_UNSUPPORTED
+    with pytest.raises(QPError) as e:
+        QPBatch([W.rt_qp(5, 100, 10, 0.1, 5)])
+    assert e.value.status == QP_ERR_UNSUPPORTED
