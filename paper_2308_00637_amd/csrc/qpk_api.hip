@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -58,7 +59,7 @@ struct qp_handle_s {
   // LDS-staged blocked PCG matvec passes
   struct Chunked {
     bool on = false;
-    int nrows = 0, ncols = 0, nchunk = 0, nwork = 0, lpr = 16;
+    int nrows = 0, ncols = 0, nchunk = 0, nwork = 0, lpr = 16, chunk_cols = kChunkCols;
     int32_t* work = nullptr;
     int32_t* rowptr = nullptr;
     uint16_t* col = nullptr;
@@ -284,7 +285,7 @@ static qp_status prepare(qp_handle h) {
 
 static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double* src) {
   ChunkArgs c{};
-  c.nrows = k.nrows; c.ncols = k.ncols; c.nchunk = k.nchunk;
+  c.nrows = k.nrows; c.ncols = k.ncols; c.nchunk = k.nchunk; c.chunk_cols = k.chunk_cols;
   c.work = k.work; c.rowptr = k.rowptr; c.col = k.col;
   c.val = lo ? k.val_lo : (const void*)k.val;
   c.src = src; c.partial = k.partial;
@@ -574,13 +575,20 @@ const char* qp_last_error(qp_handle h) { return h ? h->err.c_str() : g_create_er
 // fit one wave of blocks (one block per CU, 256 CUs).
 static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
                                const std::vector<int32_t>& col, const std::vector<double>& val,
-                               int ncols) {
+                               int ncols, int cw_default, const char* env) {
   const int64_t nrows = (int64_t)rp.size() - 1;
-  const int nchunk = (int)std::max<int64_t>(1, (ncols + kChunkCols - 1) / kChunkCols);
+  // Chunk width (columns staged in LDS per block); `env` overrides it.
+  int cw = cw_default;
+  if (const char* e = std::getenv(env)) {
+    const int v = std::atoi(e);
+    if (v >= 1024 && v <= kChunkCols) cw = v & ~1;
+  }
+  const int per_cu = std::max(1, (int)(163840 / (8 * (int64_t)cw + 1024)));
+  const int nchunk = (int)std::max<int64_t>(1, (ncols + cw - 1) / cw);
   const int64_t nnz = rp[nrows];
   std::vector<int64_t> cnt((size_t)nchunk * nrows, 0);
   for (int64_t r = 0; r < nrows; ++r)
-    for (int64_t q = rp[r]; q < rp[r + 1]; ++q) cnt[(size_t)(col[q] / kChunkCols) * nrows + r]++;
+    for (int64_t q = rp[r]; q < rp[r + 1]; ++q) cnt[(size_t)(col[q] / cw) * nrows + r]++;
   std::vector<int32_t> crp((size_t)nchunk * (nrows + 1));
   std::vector<int64_t> cnnz(nchunk, 0);
   int64_t off = 0;
@@ -600,14 +608,14 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
       for (int64_t r = 0; r < nrows; ++r) cur[(size_t)c * nrows + r] = crp[(size_t)c * (nrows + 1) + r];
     for (int64_t r = 0; r < nrows; ++r)
       for (int64_t q = rp[r]; q < rp[r + 1]; ++q) {
-        const int c = col[q] / kChunkCols;
+        const int c = col[q] / cw;
         const int64_t pos = cur[(size_t)c * nrows + r]++;
-        ccol[pos] = (uint16_t)(col[q] - c * kChunkCols);
+        ccol[pos] = (uint16_t)(col[q] - c * cw);
         cval[pos] = val[q];
       }
   }
   // work items: per chunk, proportional to its entries, rows cut at equal entry counts
-  const int target = std::max(nchunk, 256 - nchunk);
+  const int target = std::max(nchunk, 256 * per_cu - nchunk);
   std::vector<int32_t> work;
   for (int c = 0; c < nchunk; ++c) {
     const int items = (int)std::max<int64_t>(1, nnz > 0 ? (int64_t)target * cnnz[c] / nnz : 1);
@@ -630,6 +638,7 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   ck.nrows = (int)nrows;
   ck.ncols = ncols;
   ck.nchunk = nchunk;
+  ck.chunk_cols = cw;
   ck.nwork = (int)(work.size() / 3);
   ck.nnz = nnz;
   const double avg = nrows > 0 ? (double)nnz / ((double)nrows * nchunk) : 1.0;
@@ -844,8 +853,12 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(upload(h, &h->xs_col, xcol.data(), (int64_t)xcol.size()));
   CHK(upload(h, &h->xs_val, xval.data(), (int64_t)xval.size()));
   HIPCHK(chunked_set_attributes());
-  if (h->nRP > 0) CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n));
-  if (want_ck_x) CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m)));
+  // Row side: one chunk covering every column when it fits the LDS (the row
+  // epilogue then runs in place).  Column side: half-LDS chunks, two blocks
+  // per CU (measured faster on the radiation-therapy workload).
+  if (h->nRP > 0) CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, "QPK_CHUNK_COLS_R"));
+  if (want_ck_x)
+    CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, "QPK_CHUNK_COLS_X"));
   h->g_epi = grid_cap(std::max<int64_t>(n, h->nRP), kBlock, kGridMax);
   if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi;
   if (h->ck_x.on) h->g_xmv = h->ck_x.nchunk == 1 ? h->ck_x.nwork : h->g_epi;

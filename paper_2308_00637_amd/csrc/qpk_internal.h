@@ -137,9 +137,10 @@ hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st);
 // place; otherwise per-chunk partial sums are written and an epilogue kernel
 // adds them in chunk order.
 constexpr int kChunkBlock = 1024;                 // threads per block
-constexpr int kChunkCols = 20224;                 // float64 values per LDS chunk
+constexpr int kChunkCols = 20224;                 // most float64 values per LDS chunk
 struct ChunkArgs {
   int32_t nrows, ncols, nchunk;
+  int32_t chunk_cols;        // columns per chunk (<= kChunkCols); LDS = 8 * chunk_cols bytes
   const int32_t* work;       // 3 per block: chunk, r0, r1
   const int32_t* rowptr;     // nchunk * (nrows + 1)
   const uint16_t* col;

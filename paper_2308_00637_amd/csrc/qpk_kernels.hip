@@ -413,8 +413,8 @@ __global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra
     beg = rp[row];
     end = rp[row + 1];
   }
-  const int c0 = c * kChunkCols;
-  const int cw = min(kChunkCols, b.ncols - c0);
+  const int c0 = c * b.chunk_cols;
+  const int cw = min(b.chunk_cols, b.ncols - c0);
   constexpr int SP = (kChunkCols + 2 * kChunkBlock - 1) / (2 * kChunkBlock);
   const double2* __restrict__ s2 = reinterpret_cast<const double2*>(b.src + c0);
   double2 st[SP];
@@ -1042,7 +1042,7 @@ hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid,
 template <int EPI, int VK>
 static hipError_t chunked_lpr(int lpr, const ChunkArgs& c, const RowArgs& ra, const ColArgs& ca,
                               int nwork, hipStream_t st) {
-  const size_t lds = sizeof(double) * kChunkCols;
+  const size_t lds = sizeof(double) * c.chunk_cols;
   switch (lpr) {
     case 4: k_chunked<EPI, VK, 4><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
     case 8: k_chunked<EPI, VK, 8><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
