@@ -11,9 +11,15 @@ Synthetic, seeded data (the paper's clinical problems are not available).
 
 Prints one JSON line.  `value` is PCG iterations per second over the timed
 solves (inputs resident in HBM); `roofline` describes the dominant PCG
-kernel, timed with HIP events on the library's stream; `cpu_baseline` times
-the CPU oracle's matrix-free PCG on the same Newton system for a bounded
-number of iterations.
+kernel, whose dispatches are sampled (one in --profile-every) with HIP event
+pairs bound to the dispatch on the library's stream; `traffic` is read from
+the committed counter summary under profiles/ when it was taken on the same
+kernel sources; `cpu_baseline` times the CPU oracle's matrix-free PCG on the
+same Newton system for a bounded number of iterations.
+
+  python bench.py --summarize-stats rt_kernel_stats.csv --command "..."
+  python bench.py --summarize-counters fetch.csv write.csv --bench-json b.json
+turn rocprofv3 output into the summaries kept under profiles/.
 """
 import argparse
 import json
@@ -42,6 +48,15 @@ def parse():
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--profile-cap", type=int, default=20000)
+    ap.add_argument("--profile-every", type=int, default=13,
+                    help="time one dispatch in this many of each PCG kernel with HIP events")
+    ap.add_argument("--summarize-stats", metavar="CSV",
+                    help="print a markdown summary of a rocprofv3 --stats kernel_stats.csv and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the per-kernel HBM traffic summary of two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) and exit; needs --bench-json")
+    ap.add_argument("--bench-json", help="the JSON line printed by the profiled bench run")
+    ap.add_argument("--command", default="", help="the profiled command, quoted in the summary")
     return ap.parse_args()
 
 
@@ -51,24 +66,152 @@ def workload(name):
             "tiny_dense": W.tiny_dense}[name]()
 
 
-def kernel_bytes(spec, ob, cat, prec_bytes):
-    """Algorithmic HBM bytes of one launch of a PCG matvec kernel: every stored
-    operator entry once (value + int32 column), index arrays once, each vector
-    the kernel reads or writes once."""
+def kernel_bytes(spec, ob, lay, cat, prec_bytes):
+    """Algorithmic HBM bytes of one dispatch of a PCG kernel: every stored
+    operator entry once (value + uint16 column offset, one row-pointer array
+    per LDS chunk), and each vector the kernel must read or write once.  The
+    per-chunk partial sums of a multi-chunk pass are an artefact of the LDS
+    blocking and are not counted (the epilogue is charged the pass's outputs)."""
     n, m, me = spec.n, spec.m, spec.me
+    N = n + me + m
     p_rows = spec.P.shape[0] if spec.h_kind == "ptwp" else 0
     k = spec.U.shape[1] if spec.h_kind == "lowrank" else 0
+    row_out = 16 * p_rows + m * (16 + 16 + 16 + 16 + 8)   # w in, u out | lA,uA, p_lam, D, q_lam, wA
+    col_out = 8 * n * 3 + 8 * n * me                       # p_x, qdiag, q_x out, C
+    row_multi = lay["row"]["chunks"] > 1
+    col_multi = lay["col"]["chunks"] > 1
     if cat == "rowpass":
-        return (ob["row_bytes"] + 8 * n                      # operator, gathered p_x
-                + 16 * p_rows                                # w read, u write
-                + m * (16 + 16 + 16 + 16 + 8))               # lA,uA | p_lam | D | q_lam | wA
+        return ob["row_bytes"] + 8 * n + (0 if row_multi else row_out)
     if cat == "colpass":
-        return (ob["col_bytes"] + n * k * prec_bytes         # operator, dense U rows
-                + 8 * p_rows + 8 * m                         # gathered u, wA
-                + 8 * n * 3 + 8 * n * me)                    # p_x, qdiag, q_x write, C
+        return (ob["col_bytes"] + n * k * prec_bytes + 8 * p_rows + 8 * m
+                + (0 if col_multi else col_out))
+    if cat == "epilogue":
+        sides = [b for b, on in ((row_out, row_multi), (col_out, col_multi)) if on]
+        return sum(sides) / max(1, len(sides))
     if cat == "tsreduce":
         return n * k * prec_bytes + 8 * n * (1 + me)
+    if cat == "cg_update":
+        return 8 * 8 * N          # x, p, r, q, diag in; x, r, z out
+    if cat == "cg_pupdate":
+        return 3 * 8 * N          # z, p in; p out
     return 0
+
+
+def source_digest():
+    """SHA-256 over the HIP sources of the library: counter figures taken on
+    other sources do not describe the kernels that run now."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2308_00637_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(workload, precision, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary of
+    this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain device copy), or None when no summary exists or it was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_json: "):
+                rec = json.loads(line[len("traffic_json: "):])
+    if not rec or rec.get("source_sha256") != source_digest():
+        return None
+    kk = rec["kernels"].get(kernel)
+    if not kk:
+        return None
+    return 1024.0 * (kk["fetch_kib"] * rec["fetch_factor"] + kk["write_kib"] * rec["write_factor"])
+
+
+def _short(name):
+    return name.replace("void ", "").replace("qpk::", "").split("(")[0]
+
+
+def summarize_stats(path, command):
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    out = ["# rocprofv3 kernel statistics", "", f"Command: `{command}`", "",
+           "| kernel | calls | average us | total ms | % of kernel time |", "|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    print("\n".join(out))
+
+
+def summarize_counters(fetch_csv, write_csv, bench_json, command):
+    """Per-category FETCH_SIZE / WRITE_SIZE (KiB per dispatch), the factors that
+    map each counter onto the bytes of the bench's plain device copy, and the
+    machine-readable line the bench reads back (keyed to the kernel sources)."""
+    import csv
+    rec = json.loads([ln for ln in open(bench_json) if ln.startswith("{")][-1])
+    lay = rec["layout"]
+    calib = rec["copy_calibration_bytes"]
+    grid = {"row": lay["row"]["work_items"], "col": lay["col"]["work_items"]}
+
+    def category(r):
+        name, g = _short(r["Kernel_Name"]), int(r["Grid_Size"])
+        if name.startswith("k_chunked<"):
+            epi = name[len("k_chunked<"):].split(",")[0].strip()
+            if epi == "1":
+                return "rowpass"
+            if epi == "2":
+                return "colpass"
+            return "rowpass" if g == grid["row"] * 1024 and g != grid["col"] * 1024 else "colpass"
+        if name.startswith("k_rowpass<0,"):
+            return "rowpass"
+        if name.startswith("k_colpass<0,"):
+            return "colpass"
+        if name.startswith("k_chunk_epilogue"):
+            return "epilogue"
+        if name.startswith("k_ts_reduce"):
+            return "tsreduce"
+        if name in ("k_cg_update", "k_cg_pupdate"):
+            return name.replace("k_", "")
+        return None
+
+    def load(path, counter):
+        per, copy = {}, 0.0
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in r["Kernel_Name"]:
+                copy = max(copy, v)
+            c = category(r)
+            if c:
+                per.setdefault(c, []).append(v)
+        return per, copy
+
+    fetch, fcopy = load(fetch_csv, "FETCH_SIZE")
+    write, wcopy = load(write_csv, "WRITE_SIZE")
+    ff, wf = calib / (1024.0 * fcopy), calib / (1024.0 * wcopy)
+    kern = {}
+    for c in sorted(set(fetch) & set(write)):
+        kern[c] = {"fetch_kib": sum(fetch[c]) / len(fetch[c]), "write_kib": sum(write[c]) / len(write[c]),
+                   "dispatches": len(fetch[c])}
+    out = ["# rocprofv3 HBM traffic counters", "",
+           f"Command (twice, COUNTER = FETCH_SIZE then WRITE_SIZE): `{command}`", "",
+           f"Calibration: a plain device copy of {calib / 2**20:.0f} MiB reads FETCH_SIZE "
+           f"{fcopy:.0f} KiB and WRITE_SIZE {wcopy:.0f} KiB, so FETCH_SIZE is scaled by {ff:.3f} "
+           f"and WRITE_SIZE by {wf:.3f}.", "",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM MB | algorithmic MB | ratio |",
+           "|---|---|---|---|---|---|---|"]
+    for c, v in kern.items():
+        hbm = 1024.0 * (v["fetch_kib"] * ff + v["write_kib"] * wf)
+        alg = rec["kernels"].get(c, {}).get("bytes")
+        out.append(f"| {c} | {v['dispatches']} | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | "
+                   f"{hbm / 1e6:.2f} | {alg / 1e6 if alg else float('nan'):.2f} | "
+                   f"{hbm / alg if alg else float('nan'):.3f} |")
+    out += ["", "traffic_json: " + json.dumps({"source_sha256": source_digest(), "fetch_factor": ff,
+                                                "write_factor": wf, "kernels": kern})]
+    print("\n".join(out))
 
 
 def cpu_baseline(spec, iters):
@@ -98,6 +241,12 @@ def cpu_baseline(spec, iters):
 
 def main():
     args = parse()
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats, args.command)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, args.bench_json, args.command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this method's solve runs on a single "
@@ -126,7 +275,7 @@ def main():
             print(f"[bench] warmup {w}: ipm={inf.iterations} cg={inf.total_cg_iters} "
                   f"{inf.time_ms / 1e3:.2f}s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        qp.profile_begin(args.profile_cap)
+        qp.profile_begin(args.profile_cap, args.profile_every)
         infos = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -139,8 +288,11 @@ def main():
         wall = time.perf_counter() - t0
         prof = qp.profile_end()
         ob = qp.operator_bytes()
+        lay = qp.operator_layout()
+        calib = 0
         if args.copy_calib_mb > 0:
-            nb = args.copy_calib_mb * (1 << 20) // 8
+            calib = args.copy_calib_mb * (1 << 20)
+            nb = calib // 8
             a = torch.empty(nb, dtype=torch.float64, device="cuda").fill_(1.0)
             b = torch.empty_like(a)
             b.copy_(a)
@@ -152,17 +304,18 @@ def main():
 
     prec_bytes = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32x64": 4, "bf16x64": 2}[args.precision]
     kern = {}
-    for cat in ("rowpass", "colpass", "tsreduce"):
-        cnt, ms = prof[cat]
+    for cat, (cnt, ms) in prof.items():
         if cnt:
             avg_s = ms / cnt / 1e3
-            by = kernel_bytes(spec, ob, cat, prec_bytes)
+            by = kernel_bytes(spec, ob, lay, cat, prec_bytes)
             kern[cat] = {"launches_timed": cnt, "avg_us": avg_s * 1e6, "bytes": by,
                          "GBs": by / avg_s / 1e9}
     dom = max(kern, key=lambda c: kern[c]["avg_us"] * kern[c]["launches_timed"])
     d = kern[dom]
-    cgv = prof["cgvec"]
-    per_iter_us = sum(kern[c]["avg_us"] for c in kern) + (cgv[1] / cgv[0] * 1e3 if cgv[0] else 0.0)
+    # kernel time per PCG iteration (one column-side pass per iteration)
+    per_iter = kern["colpass"]["launches_timed"]
+    per_iter_us = sum(v["avg_us"] * v["launches_timed"] for v in kern.values()) / per_iter
+    traffic = stored_traffic(spec.name, args.precision, dom)
     result = {
         "metric": METRIC,
         "value": total_cg / solve_s,
@@ -189,11 +342,14 @@ def main():
         "mu_final": info.mu_final,
         "qp_create_s": t_create,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes"],
                      "launches_timed": d["launches_timed"]},
         "kernels": kern,
-        "pcg_iteration_us": per_iter_us,
+        "layout": lay,
+        "copy_calibration_bytes": calib,
+        "pcg_kernel_us_per_iteration": per_iter_us,
+        "pcg_wall_us_per_iteration": solve_s / max(1, total_cg) * 1e6,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -295,20 +295,26 @@ qp_status qp_update_data(qp_handle h, const double* c, const double* lA, const d
                          const double* b, const double* w);
 
 /* Kernel timing with HIP events on the handle's stream (instrumentation, not
- * part of the method).  qp_profile_begin(h, max_launches) pre-creates events for
- * up to max_launches timed launches per category; until qp_profile_end every
- * PCG matvec launch is bracketed by an event pair.  qp_profile_end synchronises
- * and returns, per category, the number of timed launches and their summed
+ * part of the method).  qp_profile_begin(h, max_launches, every) pre-creates
+ * events for up to max_launches timed dispatches per category; until
+ * qp_profile_end one dispatch in `every` of each PCG kernel is launched with
+ * its own event pair bound to that dispatch (hipExtLaunchKernelGGL), so a
+ * category's time is kernel execution only, comparable to a profiler's kernel
+ * trace.  A timed dispatch costs a few microseconds of queue time around it;
+ * every > 1 keeps that out of all but a sample.  qp_profile_end synchronises
+ * and returns, per category, the number of timed dispatches and their summed
  * duration in ms (HOST arrays of QP_PROF_COUNT entries), then frees the
- * events.  Categories: */
+ * events.  Categories (one kernel each): */
 enum {
-  QP_PROF_ROWPASS = 0,   /* row-side pass of K v (rows of P and A) */
-  QP_PROF_COLPASS = 1,   /* column-side pass of K v (x-part) */
-  QP_PROF_TSREDUCE = 2,  /* dense low-rank reduction U^T v, C v */
-  QP_PROF_CGVEC = 3,     /* the two PCG vector kernels of one iteration, together */
-  QP_PROF_COUNT = 4
+  QP_PROF_ROWPASS = 0,    /* row-side operator kernel of K v (rows of P and A) */
+  QP_PROF_COLPASS = 1,    /* column-side operator kernel of K v (x-part) */
+  QP_PROF_TSREDUCE = 2,   /* dense low-rank reduction U^T v, C v */
+  QP_PROF_EPILOGUE = 3,   /* sum of per-chunk partials, either side (multi-chunk only) */
+  QP_PROF_CGUPDATE = 4,   /* PCG: alpha, x, r, z, r.z */
+  QP_PROF_CGPUPDATE = 5,  /* PCG: beta, p */
+  QP_PROF_COUNT = 6
 };
-qp_status qp_profile_begin(qp_handle h, int32_t max_launches);
+qp_status qp_profile_begin(qp_handle h, int32_t max_launches, int32_t every);
 qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms);
 
 /* Bytes of the stored operators (HOST out): row-side CSR, column-side CSR,
@@ -316,6 +322,14 @@ qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms);
  * the nonzero counts of the two CSR structures. */
 qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
                             int64_t* dense_bytes, int64_t* row_nnz, int64_t* col_nnz);
+
+/* Blocked layout of the two sparse operators (HOST out arrays of 2 entries,
+ * [0] row side, [1] column side; any may be NULL): column chunks staged in LDS
+ * per work item (0 when that side runs the unblocked kernel), work items (=
+ * blocks) per pass, and columns per chunk.  With more than one chunk a pass
+ * writes per-chunk partials that a second kernel adds up. */
+qp_status qp_operator_layout(qp_handle h, int32_t* chunks, int32_t* work_items,
+                             int32_t* chunk_cols);
 
 #ifdef __cplusplus
 }

@@ -68,15 +68,18 @@ struct qp_handle_s {
     double* partial = nullptr;
     int64_t nnz = 0;
   } ck_r, ck_x;
-  int g_rmv = 1, g_xmv = 1, g_epi = 1;  // partial counts of the PCG matvec passes
+  int g_rmv = 1, g_xmv = 1;             // partial counts of the PCG matvec passes
+  int g_epi_r = 1, g_epi_x = 1;          // grids of the chunk epilogues
   double* uw = nullptr;  // [u (p_rows) | wA (m)] for the PCG matvec
   std::vector<void*> allocs;
   // optional event timing of PCG launches
   struct Prof {
     bool on = false;
     int cap = 0;
-    std::vector<hipEvent_t> ev[QP_PROF_COUNT];  // 2 per launch
-    int used[QP_PROF_COUNT] = {0, 0, 0, 0};
+    int every = 1;                               // time one dispatch in `every`
+    std::vector<hipEvent_t> ev[QP_PROF_COUNT];  // 2 per timed dispatch
+    int used[QP_PROF_COUNT] = {};
+    int64_t seen[QP_PROF_COUNT] = {};            // dispatches offered so far
   } prof;
   ~qp_handle_s() {
     for (int c = 0; c < QP_PROF_COUNT; ++c)
@@ -220,20 +223,17 @@ static TsFinishArgs tsf_args(qp_handle h) {
   return a;
 }
 
-// Event bracket for one profiled launch (no-op unless profiling is on).
-struct ProfScope {
-  qp_handle h;
-  int cat;
-  int slot = -1;
-  ProfScope(qp_handle hh, int c, bool active) : h(hh), cat(c) {
-    if (!active || !h->prof.on || h->prof.used[c] >= h->prof.cap) return;
-    slot = h->prof.used[c]++;
-    (void)hipEventRecord(h->prof.ev[c][2 * slot], h->st);
-  }
-  ~ProfScope() {
-    if (slot >= 0) (void)hipEventRecord(h->prof.ev[cat][2 * slot + 1], h->st);
-  }
-};
+// Event pair for the next dispatch of category c (null pair unless profiling
+// is on and the category still has free slots).
+static KEvents prof_slot(qp_handle h, int c, bool active) {
+  KEvents e;
+  if (!active || !h->prof.on || h->prof.used[c] >= h->prof.cap) return e;
+  if (h->prof.seen[c]++ % h->prof.every != 0) return e;
+  const int slot = h->prof.used[c]++;
+  e.start = h->prof.ev[c][2 * slot];
+  e.stop = h->prof.ev[c][2 * slot + 1];
+  return e;
+}
 
 // ---------------------------------------------------------------- steps
 // Step a1: residual stack at (x, lam, s, mu) and its norms (into sc).
@@ -306,10 +306,8 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
   if (h->has_ts) {
     TsArgs t = ts_args(h, lo, v);
     t.done = done;
-    {
-      ProfScope ps(h, QP_PROF_TSREDUCE, prof);
-      HIPCHK(launch_ts_reduce(vk, t, h->g_ts, h->st));
-    }
+    const KEvents ev = prof_slot(h, QP_PROF_TSREDUCE, prof);
+    HIPCHK(launch_ts_reduce(vk, t, h->g_ts, h->st, &ev));
     TsFinishArgs f = tsf_args(h);
     f.we = h->we_mv; f.vl = v + h->n; f.yl = y + h->n;
     f.partout = h->part + P_DOT_TS * kGridMax; f.done = done;
@@ -323,37 +321,39 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     a.vl = h->m > 0 ? v + h->n : v;
     a.dl = h->dl; a.yl = y + h->n;
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
-    ProfScope ps(h, QP_PROF_ROWPASS, prof);
+    const KEvents ev = prof_slot(h, QP_PROF_ROWPASS, prof);
     if (h->ck_r.on) {
       ChunkArgs ca = chunk_args(h->ck_r, lo, v);
       if (h->ck_r.nchunk == 1) {
-        HIPCHK(launch_chunked(CE_ROW, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st));
+        HIPCHK(launch_chunked(CE_ROW, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st, &ev));
       } else {
-        HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st));
-        HIPCHK(launch_chunk_epilogue_row(ca, a, h->g_epi, h->st));
+        HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st,
+                              &ev));
+        const KEvents ee = prof_slot(h, QP_PROF_EPILOGUE, prof);
+        HIPCHK(launch_chunk_epilogue_row(ca, a, h->g_epi_r, h->st, &ee));
       }
     } else {
-      HIPCHK(launch_rowpass(R_MATVEC, vk, h->lpr_r, a, h->g_rmv, h->st));
+      HIPCHK(launch_rowpass(R_MATVEC, vk, h->lpr_r, a, h->g_rmv, h->st, &ev));
     }
   }
   ColArgs c = col_args(h, lo);
   c.src_hx = v; c.src_pt = h->u; c.src_at = h->wA_mv; c.we = h->we_mv; c.v = v; c.y = y;
   c.part0 = h->part + P_DOT_X * kGridMax; c.done = done; c.bump = bump;
-  {
-    ProfScope ps(h, QP_PROF_COLPASS, prof);
-    if (h->ck_x.on) {
-      ChunkArgs ca = chunk_args(h->ck_x, lo, h->uw);
-      if (h->ck_x.nchunk == 1) {
-        HIPCHK(launch_chunked(CE_COL, vk, h->ck_x.lpr, ca, RowArgs{}, c, h->ck_x.nwork, h->st));
-      } else {
-        ColArgs c0 = c;
-        c0.bump = nullptr;
-        HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_x.lpr, ca, RowArgs{}, c0, h->ck_x.nwork, h->st));
-        HIPCHK(launch_chunk_epilogue_col(ca, c, h->g_epi, h->st));
-      }
+  const KEvents ev = prof_slot(h, QP_PROF_COLPASS, prof);
+  if (h->ck_x.on) {
+    ChunkArgs ca = chunk_args(h->ck_x, lo, h->uw);
+    if (h->ck_x.nchunk == 1) {
+      HIPCHK(launch_chunked(CE_COL, vk, h->ck_x.lpr, ca, RowArgs{}, c, h->ck_x.nwork, h->st, &ev));
     } else {
-      HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_xmv, h->st));
+      ColArgs c0 = c;
+      c0.bump = nullptr;
+      HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_x.lpr, ca, RowArgs{}, c0, h->ck_x.nwork, h->st,
+                            &ev));
+      const KEvents ee = prof_slot(h, QP_PROF_EPILOGUE, prof);
+      HIPCHK(launch_chunk_epilogue_col(ca, c, h->g_epi_x, h->st, &ee));
     }
+  } else {
+    HIPCHK(launch_colpass(X_MATVEC, vk, h->lpr_x, c, h->g_xmv, h->st, &ev));
   }
   return QP_OK;
 }
@@ -404,9 +404,10 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
           HIPCHK(launch_cg_restart(a, h->tmp, 0, h->st));
         }
         CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT));
-        ProfScope ps(h, QP_PROF_CGVEC, true);
-        HIPCHK(launch_cg_update(a, h->st));
-        HIPCHK(launch_cg_pupdate(a, h->st));
+        const KEvents e1 = prof_slot(h, QP_PROF_CGUPDATE, true);
+        HIPCHK(launch_cg_update(a, h->st, &e1));
+        const KEvents e2 = prof_slot(h, QP_PROF_CGPUPDATE, true);
+        HIPCHK(launch_cg_pupdate(a, h->st, &e2));
       }
       HIPCHK(hipMemcpyAsync(h->hfl, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
       HIPCHK(hipStreamSynchronize(h->st));
@@ -859,9 +860,10 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   if (h->nRP > 0) CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, "QPK_CHUNK_COLS_R"));
   if (want_ck_x)
     CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, "QPK_CHUNK_COLS_X"));
-  h->g_epi = grid_cap(std::max<int64_t>(n, h->nRP), kBlock, kGridMax);
-  if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi;
-  if (h->ck_x.on) h->g_xmv = h->ck_x.nchunk == 1 ? h->ck_x.nwork : h->g_epi;
+  h->g_epi_r = grid_cap(std::max<int64_t>(h->nRP, 1), kBlock, kGridMax);
+  h->g_epi_x = grid_cap(n, kBlock, kGridMax);
+  if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi_r;
+  if (h->ck_x.on) h->g_xmv = h->ck_x.nchunk == 1 ? h->ck_x.nwork : h->g_epi_x;
   if (k > 0) {
     CHK(upload(h, &h->U, d->U, n * k));
     CHK(upload(h, &h->wd, d->wd, k));
@@ -1283,15 +1285,17 @@ qp_status qp_update_data(qp_handle h, const double* c, const double* lA, const d
   return QP_OK;
 }
 
-qp_status qp_profile_begin(qp_handle h, int32_t max_launches) {
-  if (!h || max_launches < 1) return QP_ERR_ARG;
+qp_status qp_profile_begin(qp_handle h, int32_t max_launches, int32_t every) {
+  if (!h || max_launches < 1 || every < 1) return QP_ERR_ARG;
   for (int c = 0; c < QP_PROF_COUNT; ++c) {
     for (hipEvent_t e : h->prof.ev[c]) (void)hipEventDestroy(e);
     h->prof.ev[c].assign(2 * (size_t)max_launches, nullptr);
     for (auto& e : h->prof.ev[c]) HIPCHK(hipEventCreate(&e));
     h->prof.used[c] = 0;
+    h->prof.seen[c] = 0;
   }
   h->prof.cap = max_launches;
+  h->prof.every = every;
   h->prof.on = true;
   return QP_OK;
 }
@@ -1332,6 +1336,19 @@ qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
   if (dense_bytes) *dense_bytes = (int64_t)h->n * h->k * vb;
   if (row_nnz) *row_nnz = h->nnz_rp;
   if (col_nnz) *col_nnz = h->nnz_xs;
+  return QP_OK;
+}
+
+qp_status qp_operator_layout(qp_handle h, int32_t* chunks, int32_t* work_items,
+                             int32_t* chunk_cols) {
+  if (!h) return QP_ERR_ARG;
+  const qp_handle_s::Chunked* side[2] = {&h->ck_r, &h->ck_x};
+  for (int i = 0; i < 2; ++i) {
+    const bool on = side[i]->on;
+    if (chunks) chunks[i] = on ? side[i]->nchunk : 0;
+    if (work_items) work_items[i] = on ? side[i]->nwork : (i == 0 ? h->g_rmv : h->g_xmv);
+    if (chunk_cols) chunk_cols[i] = on ? side[i]->chunk_cols : 0;
+  }
   return QP_OK;
 }
 

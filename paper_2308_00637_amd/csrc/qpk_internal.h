@@ -9,6 +9,7 @@
 // per-voxel values u), column j of A (gathers the per-row values wA).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace qpk {
@@ -124,10 +125,29 @@ struct TsArgs {
   const int* done;
 };
 
+// Optional timing of a single dispatch.  With start set, the launcher issues
+// the kernel through hipExtLaunchKernelGGL, which ties both events to that
+// dispatch alone (no queue gap before or after it is counted).
+struct KEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+template <typename F, typename... A>
+inline hipError_t launch_ev(const KEvents* ev, F kern, dim3 grid, dim3 block, uint32_t lds,
+                            hipStream_t st, A... args) {
+  if (ev && ev->start)
+    hipExtLaunchKernelGGL(kern, grid, block, lds, st, ev->start, ev->stop, 0u, args...);
+  else
+    kern<<<grid, block, lds, st>>>(args...);
+  return hipGetLastError();
+}
+
 // Launchers (defined in qpk_kernels.hip).  lpr: lanes per row (4..64).
-hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid, hipStream_t st);
-hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid, hipStream_t st);
-hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st);
+hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid, hipStream_t st,
+                          const KEvents* ev = nullptr);
+hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid, hipStream_t st,
+                          const KEvents* ev = nullptr);
+hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st,
+                            const KEvents* ev = nullptr);
 
 // LDS-staged 2-D blocked passes.  The columns of a CSR operator are cut into
 // chunks of kChunkCols; chunk c stores its own CSR (rowptr c*(nrows+1) ...,
@@ -150,9 +170,11 @@ struct ChunkArgs {
 };
 enum ChunkEpi : int { CE_PARTIAL = 0, CE_ROW = 1, CE_COL = 2 };
 hipError_t launch_chunked(int epi, int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
-                          const ColArgs& ca, int nwork, hipStream_t st);
-hipError_t launch_chunk_epilogue_col(const ChunkArgs& c, const ColArgs& ca, int grid, hipStream_t st);
-hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int grid, hipStream_t st);
+                          const ColArgs& ca, int nwork, hipStream_t st, const KEvents* ev = nullptr);
+hipError_t launch_chunk_epilogue_col(const ChunkArgs& c, const ColArgs& ca, int grid, hipStream_t st,
+                                     const KEvents* ev = nullptr);
+hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int grid, hipStream_t st,
+                                     const KEvents* ev = nullptr);
 hipError_t chunked_set_attributes();
 
 }  // namespace qpk
@@ -251,8 +273,8 @@ struct CgArgs {
   int maxit;
 };
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t st);
-hipError_t launch_cg_update(const CgArgs& a, hipStream_t st);
-hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st);
+hipError_t launch_cg_update(const CgArgs& a, hipStream_t st, const KEvents* ev = nullptr);
+hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st, const KEvents* ev = nullptr);
 hipError_t launch_cg_restart(const CgArgs& a, const double* kx, int resume, hipStream_t st);
 
 // Backward: gradient outputs from the adjoint solution u (K-vector layout).

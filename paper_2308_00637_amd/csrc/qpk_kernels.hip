@@ -980,94 +980,98 @@ static inline int grid_for(int64_t items, int per_block) {
 }
 
 template <int MODE, int VK>
-static hipError_t rowpass_lpr(int lpr, const RowArgs& a, int grid, hipStream_t st) {
+static hipError_t rowpass_lpr(int lpr, const RowArgs& a, int grid, hipStream_t st,
+                              const KEvents* ev) {
   switch (lpr) {
-    case 4: k_rowpass<MODE, VK, 4><<<grid, kBlock, 0, st>>>(a); break;
-    case 8: k_rowpass<MODE, VK, 8><<<grid, kBlock, 0, st>>>(a); break;
-    case 16: k_rowpass<MODE, VK, 16><<<grid, kBlock, 0, st>>>(a); break;
-    case 32: k_rowpass<MODE, VK, 32><<<grid, kBlock, 0, st>>>(a); break;
-    default: k_rowpass<MODE, VK, 64><<<grid, kBlock, 0, st>>>(a); break;
+    case 4: return launch_ev(ev, k_rowpass<MODE, VK, 4>, dim3(grid), dim3(kBlock), 0, st, a);
+    case 8: return launch_ev(ev, k_rowpass<MODE, VK, 8>, dim3(grid), dim3(kBlock), 0, st, a);
+    case 16: return launch_ev(ev, k_rowpass<MODE, VK, 16>, dim3(grid), dim3(kBlock), 0, st, a);
+    case 32: return launch_ev(ev, k_rowpass<MODE, VK, 32>, dim3(grid), dim3(kBlock), 0, st, a);
+    default: return launch_ev(ev, k_rowpass<MODE, VK, 64>, dim3(grid), dim3(kBlock), 0, st, a);
   }
   return hipGetLastError();
 }
 
 template <int MODE, int VK>
-static hipError_t colpass_lpr(int lpr, const ColArgs& a, int grid, hipStream_t st) {
+static hipError_t colpass_lpr(int lpr, const ColArgs& a, int grid, hipStream_t st,
+                              const KEvents* ev) {
   switch (lpr) {
-    case 4: k_colpass<MODE, VK, 4><<<grid, kBlock, 0, st>>>(a); break;
-    case 8: k_colpass<MODE, VK, 8><<<grid, kBlock, 0, st>>>(a); break;
-    case 16: k_colpass<MODE, VK, 16><<<grid, kBlock, 0, st>>>(a); break;
-    case 32: k_colpass<MODE, VK, 32><<<grid, kBlock, 0, st>>>(a); break;
-    default: k_colpass<MODE, VK, 64><<<grid, kBlock, 0, st>>>(a); break;
+    case 4: return launch_ev(ev, k_colpass<MODE, VK, 4>, dim3(grid), dim3(kBlock), 0, st, a);
+    case 8: return launch_ev(ev, k_colpass<MODE, VK, 8>, dim3(grid), dim3(kBlock), 0, st, a);
+    case 16: return launch_ev(ev, k_colpass<MODE, VK, 16>, dim3(grid), dim3(kBlock), 0, st, a);
+    case 32: return launch_ev(ev, k_colpass<MODE, VK, 32>, dim3(grid), dim3(kBlock), 0, st, a);
+    default: return launch_ev(ev, k_colpass<MODE, VK, 64>, dim3(grid), dim3(kBlock), 0, st, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid, hipStream_t st) {
+hipError_t launch_rowpass(int mode, int vk, int lpr, const RowArgs& a, int grid, hipStream_t st,
+                          const KEvents* ev) {
   if (mode == R_MATVEC) {
-    if (vk == VK_F32) return rowpass_lpr<R_MATVEC, VK_F32>(lpr, a, grid, st);
-    if (vk == VK_BF16) return rowpass_lpr<R_MATVEC, VK_BF16>(lpr, a, grid, st);
-    if (vk == VK_F32X) return rowpass_lpr<R_MATVEC, VK_F32X>(lpr, a, grid, st);
-    if (vk == VK_BF16X) return rowpass_lpr<R_MATVEC, VK_BF16X>(lpr, a, grid, st);
-    return rowpass_lpr<R_MATVEC, VK_F64>(lpr, a, grid, st);
+    if (vk == VK_F32) return rowpass_lpr<R_MATVEC, VK_F32>(lpr, a, grid, st, ev);
+    if (vk == VK_BF16) return rowpass_lpr<R_MATVEC, VK_BF16>(lpr, a, grid, st, ev);
+    if (vk == VK_F32X) return rowpass_lpr<R_MATVEC, VK_F32X>(lpr, a, grid, st, ev);
+    if (vk == VK_BF16X) return rowpass_lpr<R_MATVEC, VK_BF16X>(lpr, a, grid, st, ev);
+    return rowpass_lpr<R_MATVEC, VK_F64>(lpr, a, grid, st, ev);
   }
   switch (mode) {
-    case R_RESID: return rowpass_lpr<R_RESID, VK_F64>(lpr, a, grid, st);
-    case R_RECOVER: return rowpass_lpr<R_RECOVER, VK_F64>(lpr, a, grid, st);
-    case R_GRADW: return rowpass_lpr<R_GRADW, VK_F64>(lpr, a, grid, st);
-    case R_PU: return rowpass_lpr<R_PU, VK_F64>(lpr, a, grid, st);
-    case R_INIT: return rowpass_lpr<R_INIT, VK_F64>(lpr, a, grid, st);
+    case R_RESID: return rowpass_lpr<R_RESID, VK_F64>(lpr, a, grid, st, ev);
+    case R_RECOVER: return rowpass_lpr<R_RECOVER, VK_F64>(lpr, a, grid, st, ev);
+    case R_GRADW: return rowpass_lpr<R_GRADW, VK_F64>(lpr, a, grid, st, ev);
+    case R_PU: return rowpass_lpr<R_PU, VK_F64>(lpr, a, grid, st, ev);
+    case R_INIT: return rowpass_lpr<R_INIT, VK_F64>(lpr, a, grid, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid, hipStream_t st) {
+hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid, hipStream_t st,
+                          const KEvents* ev) {
   if (mode == X_MATVEC) {
-    if (vk == VK_F32) return colpass_lpr<X_MATVEC, VK_F32>(lpr, a, grid, st);
-    if (vk == VK_BF16) return colpass_lpr<X_MATVEC, VK_BF16>(lpr, a, grid, st);
-    if (vk == VK_F32X) return colpass_lpr<X_MATVEC, VK_F32X>(lpr, a, grid, st);
-    if (vk == VK_BF16X) return colpass_lpr<X_MATVEC, VK_BF16X>(lpr, a, grid, st);
-    return colpass_lpr<X_MATVEC, VK_F64>(lpr, a, grid, st);
+    if (vk == VK_F32) return colpass_lpr<X_MATVEC, VK_F32>(lpr, a, grid, st, ev);
+    if (vk == VK_BF16) return colpass_lpr<X_MATVEC, VK_BF16>(lpr, a, grid, st, ev);
+    if (vk == VK_F32X) return colpass_lpr<X_MATVEC, VK_F32X>(lpr, a, grid, st, ev);
+    if (vk == VK_BF16X) return colpass_lpr<X_MATVEC, VK_BF16X>(lpr, a, grid, st, ev);
+    return colpass_lpr<X_MATVEC, VK_F64>(lpr, a, grid, st, ev);
   }
   switch (mode) {
-    case X_RESID: return colpass_lpr<X_RESID, VK_F64>(lpr, a, grid, st);
-    case X_RHS: return colpass_lpr<X_RHS, VK_F64>(lpr, a, grid, st);
-    case X_DIAGH: return colpass_lpr<X_DIAGH, VK_F64>(lpr, a, grid, st);
-    case X_CEFF: return colpass_lpr<X_CEFF, VK_F64>(lpr, a, grid, st);
-    case X_OBJ: return colpass_lpr<X_OBJ, VK_F64>(lpr, a, grid, st);
+    case X_RESID: return colpass_lpr<X_RESID, VK_F64>(lpr, a, grid, st, ev);
+    case X_RHS: return colpass_lpr<X_RHS, VK_F64>(lpr, a, grid, st, ev);
+    case X_DIAGH: return colpass_lpr<X_DIAGH, VK_F64>(lpr, a, grid, st, ev);
+    case X_CEFF: return colpass_lpr<X_CEFF, VK_F64>(lpr, a, grid, st, ev);
+    case X_OBJ: return colpass_lpr<X_OBJ, VK_F64>(lpr, a, grid, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int EPI, int VK>
 static hipError_t chunked_lpr(int lpr, const ChunkArgs& c, const RowArgs& ra, const ColArgs& ca,
-                              int nwork, hipStream_t st) {
+                              int nwork, hipStream_t st, const KEvents* ev) {
   const size_t lds = sizeof(double) * c.chunk_cols;
   switch (lpr) {
-    case 4: k_chunked<EPI, VK, 4><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
-    case 8: k_chunked<EPI, VK, 8><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
-    case 16: k_chunked<EPI, VK, 16><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
-    case 32: k_chunked<EPI, VK, 32><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
-    default: k_chunked<EPI, VK, 64><<<nwork, kChunkBlock, lds, st>>>(c, ra, ca); break;
+    case 4: return launch_ev(ev, k_chunked<EPI, VK, 4>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
+    case 8: return launch_ev(ev, k_chunked<EPI, VK, 8>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
+    case 16: return launch_ev(ev, k_chunked<EPI, VK, 16>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
+    case 32: return launch_ev(ev, k_chunked<EPI, VK, 32>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
+    default: return launch_ev(ev, k_chunked<EPI, VK, 64>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
   }
   return hipGetLastError();
 }
 
 template <int EPI>
 static hipError_t chunked_vk(int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
-                             const ColArgs& ca, int nwork, hipStream_t st) {
-  if (vk == VK_F32) return chunked_lpr<EPI, VK_F32>(lpr, c, ra, ca, nwork, st);
-  if (vk == VK_BF16) return chunked_lpr<EPI, VK_BF16>(lpr, c, ra, ca, nwork, st);
-  if (vk == VK_F32X) return chunked_lpr<EPI, VK_F32X>(lpr, c, ra, ca, nwork, st);
-  if (vk == VK_BF16X) return chunked_lpr<EPI, VK_BF16X>(lpr, c, ra, ca, nwork, st);
-  return chunked_lpr<EPI, VK_F64>(lpr, c, ra, ca, nwork, st);
+                             const ColArgs& ca, int nwork, hipStream_t st, const KEvents* ev) {
+  if (vk == VK_F32) return chunked_lpr<EPI, VK_F32>(lpr, c, ra, ca, nwork, st, ev);
+  if (vk == VK_BF16) return chunked_lpr<EPI, VK_BF16>(lpr, c, ra, ca, nwork, st, ev);
+  if (vk == VK_F32X) return chunked_lpr<EPI, VK_F32X>(lpr, c, ra, ca, nwork, st, ev);
+  if (vk == VK_BF16X) return chunked_lpr<EPI, VK_BF16X>(lpr, c, ra, ca, nwork, st, ev);
+  return chunked_lpr<EPI, VK_F64>(lpr, c, ra, ca, nwork, st, ev);
 }
 
 hipError_t launch_chunked(int epi, int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
-                          const ColArgs& ca, int nwork, hipStream_t st) {
-  if (epi == CE_ROW) return chunked_vk<CE_ROW>(vk, lpr, c, ra, ca, nwork, st);
-  if (epi == CE_COL) return chunked_vk<CE_COL>(vk, lpr, c, ra, ca, nwork, st);
-  return chunked_vk<CE_PARTIAL>(vk, lpr, c, ra, ca, nwork, st);
+                          const ColArgs& ca, int nwork, hipStream_t st, const KEvents* ev) {
+  if (epi == CE_ROW) return chunked_vk<CE_ROW>(vk, lpr, c, ra, ca, nwork, st, ev);
+  if (epi == CE_COL) return chunked_vk<CE_COL>(vk, lpr, c, ra, ca, nwork, st, ev);
+  return chunked_vk<CE_PARTIAL>(vk, lpr, c, ra, ca, nwork, st, ev);
 }
 
 template <int EPI, int VK>
@@ -1106,23 +1110,23 @@ hipError_t chunked_set_attributes() {
   return e;
 }
 
-hipError_t launch_chunk_epilogue_col(const ChunkArgs& c, const ColArgs& ca, int grid, hipStream_t st) {
-  k_chunk_epilogue_col<<<grid, kBlock, 0, st>>>(c, ca);
-  return hipGetLastError();
+hipError_t launch_chunk_epilogue_col(const ChunkArgs& c, const ColArgs& ca, int grid, hipStream_t st,
+                                     const KEvents* ev) {
+  return launch_ev(ev, k_chunk_epilogue_col, dim3(grid), dim3(kBlock), 0, st, c, ca);
 }
 
-hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int grid, hipStream_t st) {
-  k_chunk_epilogue_row<<<grid, kBlock, 0, st>>>(c, ra);
-  return hipGetLastError();
+hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int grid, hipStream_t st,
+                                     const KEvents* ev) {
+  return launch_ev(ev, k_chunk_epilogue_row, dim3(grid), dim3(kBlock), 0, st, c, ra);
 }
 
-hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st) {
-  if (vk == VK_F32) k_ts_reduce<VK_F32><<<grid, kBlock, 0, st>>>(a);
-  else if (vk == VK_BF16) k_ts_reduce<VK_BF16><<<grid, kBlock, 0, st>>>(a);
-  else if (vk == VK_F32X) k_ts_reduce<VK_F32X><<<grid, kBlock, 0, st>>>(a);
-  else if (vk == VK_BF16X) k_ts_reduce<VK_BF16X><<<grid, kBlock, 0, st>>>(a);
-  else k_ts_reduce<VK_F64><<<grid, kBlock, 0, st>>>(a);
-  return hipGetLastError();
+hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st, const KEvents* ev) {
+  const dim3 g(grid), b(kBlock);
+  if (vk == VK_F32) return launch_ev(ev, k_ts_reduce<VK_F32>, g, b, 0, st, a);
+  if (vk == VK_BF16) return launch_ev(ev, k_ts_reduce<VK_BF16>, g, b, 0, st, a);
+  if (vk == VK_F32X) return launch_ev(ev, k_ts_reduce<VK_F32X>, g, b, 0, st, a);
+  if (vk == VK_BF16X) return launch_ev(ev, k_ts_reduce<VK_BF16X>, g, b, 0, st, a);
+  return launch_ev(ev, k_ts_reduce<VK_F64>, g, b, 0, st, a);
 }
 
 hipError_t launch_ts_finish(int mode, const TsFinishArgs& a, hipStream_t st) {
@@ -1171,13 +1175,11 @@ hipError_t launch_cg_init(const CgArgs& a, hipStream_t st) {
   k_cg_init_finish<<<1, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
-hipError_t launch_cg_update(const CgArgs& a, hipStream_t st) {
-  k_cg_update<<<a.g_vec, kBlock, 0, st>>>(a);
-  return hipGetLastError();
+hipError_t launch_cg_update(const CgArgs& a, hipStream_t st, const KEvents* ev) {
+  return launch_ev(ev, k_cg_update, dim3(a.g_vec), dim3(kBlock), 0, st, a);
 }
-hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st) {
-  k_cg_pupdate<<<a.g_vec, kBlock, 0, st>>>(a);
-  return hipGetLastError();
+hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st, const KEvents* ev) {
+  return launch_ev(ev, k_cg_pupdate, dim3(a.g_vec), dim3(kBlock), 0, st, a);
 }
 hipError_t launch_cg_restart(const CgArgs& a, const double* kx, int resume, hipStream_t st) {
   k_cg_restart<<<a.g_vec, kBlock, 0, st>>>(a, kx, resume);

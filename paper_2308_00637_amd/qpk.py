@@ -81,11 +81,12 @@ EXPORTS = [
     "qp_create", "qp_destroy", "qp_set_stream", "qp_sizes", "qp_set_state", "qp_get_state",
     "qp_init_state", "qp_residuals", "qp_newton_rhs", "qp_kkt_matvec", "kkt_pcg_solve",
     "qp_newton_direction", "qp_step_lengths", "qp_take_step", "ipm_solve", "qp_backward",
-    "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_update_data",
+    "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_operator_layout",
+    "qp_update_data",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
     "qp_batch_last_error",
 ]
-PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "cgvec")
+PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate")
 
 
 def _load():
@@ -115,9 +116,10 @@ def _load():
         "qp_take_step": (C.c_int, [vp, vp, vp, vp, C.c_double, C.c_double]),
         "ipm_solve": (C.c_int, [vp, C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo)]),
         "qp_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.POINTER(PcgOptions), C.POINTER(PcgInfo)]),
-        "qp_profile_begin": (C.c_int, [vp, C.c_int32]),
+        "qp_profile_begin": (C.c_int, [vp, C.c_int32, C.c_int32]),
         "qp_profile_end": (C.c_int, [vp, _i64p, _dp]),
         "qp_operator_bytes": (C.c_int, [vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
+        "qp_operator_layout": (C.c_int, [vp, _i32p, _i32p, _i32p]),
         "qp_update_data": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "qp_batch_create": (C.c_int, [C.POINTER(QpDesc), C.c_int32, vp, C.POINTER(vp)]),
         "qp_batch_destroy": (None, [vp]),
@@ -359,12 +361,13 @@ class QP:
     def update_data(self, c=None, lA=None, uA=None, b=None, w=None):
         self._check(LIB.qp_update_data(self.h, _dev(c), _dev(lA), _dev(uA), _dev(b), _dev(w)))
 
-    def profile_begin(self, max_launches: int):
-        self._check(LIB.qp_profile_begin(self.h, int(max_launches)))
+    def profile_begin(self, max_launches: int, every: int = 1):
+        """Time up to max_launches dispatches per PCG kernel, one in `every`."""
+        self._check(LIB.qp_profile_begin(self.h, int(max_launches), int(every)))
 
     def profile_end(self):
-        cnt = (C.c_int64 * 4)()
-        ms = (C.c_double * 4)()
+        cnt = (C.c_int64 * len(PROF_CATEGORIES))()
+        ms = (C.c_double * len(PROF_CATEGORIES))()
         self._check(LIB.qp_profile_end(self.h, cnt, ms))
         return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(PROF_CATEGORIES)}
 
@@ -373,6 +376,14 @@ class QP:
         self._check(LIB.qp_operator_bytes(self.h, *[C.byref(x) for x in v]))
         return dict(zip(("row_bytes", "col_bytes", "dense_bytes", "row_nnz", "col_nnz"),
                         [int(x.value) for x in v]))
+
+    def operator_layout(self):
+        """Blocked layout per side (row, column): LDS column chunks, work items
+        per pass, columns per chunk."""
+        arr = [(C.c_int32 * 2)() for _ in range(3)]
+        self._check(LIB.qp_operator_layout(self.h, *arr))
+        return {side: {"chunks": int(arr[0][i]), "work_items": int(arr[1][i]),
+                       "chunk_cols": int(arr[2][i])} for i, side in enumerate(("row", "col"))}
 
     def backward(self, grad_x, want=("c", "lA", "uA", "b", "w"), opts: Optional[PcgOptions] = None):
         n, sz = self.sizes.n, self.sizes
