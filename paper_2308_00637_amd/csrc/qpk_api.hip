@@ -59,14 +59,15 @@ struct qp_handle_s {
   // LDS-staged blocked PCG matvec passes
   struct Chunked {
     bool on = false;
-    int nrows = 0, ncols = 0, nchunk = 0, nwork = 0, lpr = 16, chunk_cols = kChunkCols;
+    int nrows = 0, ncols = 0, nchunk = 0, nwork = 0, lpr = 16, chunk_cols = kChunkCols, kv = kKvDefault;
     int32_t* work = nullptr;
     int32_t* rowptr = nullptr;
     uint16_t* col = nullptr;
     double* val = nullptr;
     void* val_lo = nullptr;
     double* partial = nullptr;
-    int64_t nnz = 0;
+    int64_t nnz = 0;      // entries of the operator
+    int64_t stored = 0;   // entries stored (segments padded to even length)
   } ck_r, ck_x;
   int g_rmv = 1, g_xmv = 1;             // partial counts of the PCG matvec passes
   int g_epi_r = 1, g_epi_x = 1;          // grids of the chunk epilogues
@@ -289,6 +290,8 @@ static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double
   c.work = k.work; c.rowptr = k.rowptr; c.col = k.col;
   c.val = lo ? k.val_lo : (const void*)k.val;
   c.src = src; c.partial = k.partial;
+  c.kv = k.kv;
+  c.nstored = (int32_t)k.stored;
   return c;
 }
 
@@ -576,7 +579,8 @@ const char* qp_last_error(qp_handle h) { return h ? h->err.c_str() : g_create_er
 // fit one wave of blocks (one block per CU, 256 CUs).
 static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
                                const std::vector<int32_t>& col, const std::vector<double>& val,
-                               int ncols, int cw_default, const char* env) {
+                               int ncols, int cw_default, int kv_default, const char* env,
+                               const char* env_lpr, const char* env_kv) {
   const int64_t nrows = (int64_t)rp.size() - 1;
   // Chunk width (columns staged in LDS per block); `env` overrides it.
   int cw = cw_default;
@@ -590,19 +594,26 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   std::vector<int64_t> cnt((size_t)nchunk * nrows, 0);
   for (int64_t r = 0; r < nrows; ++r)
     for (int64_t q = rp[r]; q < rp[r + 1]; ++q) cnt[(size_t)(col[q] / cw) * nrows + r]++;
+  // each (chunk, row) segment is padded with zero entries to even length, so
+  // the kernel loads entries in aligned pairs
   std::vector<int32_t> crp((size_t)nchunk * (nrows + 1));
   std::vector<int64_t> cnnz(nchunk, 0);
   int64_t off = 0;
   for (int c = 0; c < nchunk; ++c) {
     for (int64_t r = 0; r < nrows; ++r) {
       crp[(size_t)c * (nrows + 1) + r] = (int32_t)off;
-      off += cnt[(size_t)c * nrows + r];
+      off += (cnt[(size_t)c * nrows + r] + 1) & ~int64_t(1);
+      if (off * 8 >= (int64_t(1) << 31)) {   // byte offsets of the kernel's buffer loads
+        h->err = "blocked operator exceeds 2^28 stored entries";
+        return QP_ERR_UNSUPPORTED;
+      }
     }
     crp[(size_t)c * (nrows + 1) + nrows] = (int32_t)off;
     cnnz[c] = crp[(size_t)c * (nrows + 1) + nrows] - crp[(size_t)c * (nrows + 1)];
   }
-  std::vector<uint16_t> ccol(nnz);
-  std::vector<double> cval(nnz);
+  const int64_t stored = off;
+  std::vector<uint16_t> ccol(stored, 0);
+  std::vector<double> cval(stored, 0.0);
   {
     std::vector<int64_t> cur(cnt.size());
     for (int c = 0; c < nchunk; ++c)
@@ -619,7 +630,8 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   const int target = std::max(nchunk, 256 * per_cu - nchunk);
   std::vector<int32_t> work;
   for (int c = 0; c < nchunk; ++c) {
-    const int items = (int)std::max<int64_t>(1, nnz > 0 ? (int64_t)target * cnnz[c] / nnz : 1);
+    const int items =
+        (int)std::max<int64_t>(1, stored > 0 ? (int64_t)target * cnnz[c] / stored : 1);
     const int32_t* base = &crp[(size_t)c * (nrows + 1)];
     int64_t r = 0;
     for (int it = 0; it < items; ++it) {
@@ -642,12 +654,16 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   ck.chunk_cols = cw;
   ck.nwork = (int)(work.size() / 3);
   ck.nnz = nnz;
+  ck.stored = stored;
   const double avg = nrows > 0 ? (double)nnz / ((double)nrows * nchunk) : 1.0;
   ck.lpr = pow2_clamp(avg / 4.0, 4, 64);
+  if (const char* e = std::getenv(env_lpr)) ck.lpr = pow2_clamp(std::atof(e), 4, 64);
+  ck.kv = kv_default;
+  if (const char* e = std::getenv(env_kv)) ck.kv = std::atoi(e) & 1;
   CHK(upload(h, &ck.work, work.data(), (int64_t)work.size()));
   CHK(upload(h, &ck.rowptr, crp.data(), (int64_t)crp.size()));
-  CHK(upload(h, &ck.col, ccol.data(), nnz));
-  CHK(upload(h, &ck.val, cval.data(), nnz));
+  CHK(upload(h, &ck.col, ccol.data(), stored));
+  CHK(upload(h, &ck.val, cval.data(), stored));
   if (h->vk != VK_F64) CHK(upload_lo(h, &ck.val_lo, cval));
   if (nchunk > 1) CHK(dalloc_t(h, &ck.partial, (int64_t)nchunk * nrows));
   HIPCHK(hipStreamSynchronize(h->st));  // host staging vectors go out of scope
@@ -855,11 +871,15 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(upload(h, &h->xs_val, xval.data(), (int64_t)xval.size()));
   HIPCHK(chunked_set_attributes());
   // Row side: one chunk covering every column when it fits the LDS (the row
-  // epilogue then runs in place).  Column side: half-LDS chunks, two blocks
-  // per CU (measured faster on the radiation-therapy workload).
-  if (h->nRP > 0) CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, "QPK_CHUNK_COLS_R"));
+  // epilogue then runs in place), staged through registers.  Column side:
+  // half-LDS chunks staged straight into LDS, two blocks per CU (both
+  // measured fastest on the radiation-therapy workload).
+  if (h->nRP > 0)
+    CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, "QPK_CHUNK_COLS_R",
+                      "QPK_LPR_R", "QPK_KV_R"));
   if (want_ck_x)
-    CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, "QPK_CHUNK_COLS_X"));
+    CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1,
+                      "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
   h->g_epi_r = grid_cap(std::max<int64_t>(h->nRP, 1), kBlock, kGridMax);
   h->g_epi_x = grid_cap(n, kBlock, kGridMax);
   if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi_r;

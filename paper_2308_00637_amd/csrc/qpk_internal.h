@@ -167,7 +167,10 @@ struct ChunkArgs {
   const void* val;
   const double* src;         // gathered vector (ncols)
   double* partial;           // nchunk * nrows when nchunk > 1
+  int32_t nstored;           // stored entries (with the even-length padding)
+  int32_t kv;                // chunk staging: 0 through registers, 1 direct to LDS
 };
+constexpr int kKvDefault = 1;
 enum ChunkEpi : int { CE_PARTIAL = 0, CE_ROW = 1, CE_COL = 2 };
 hipError_t launch_chunked(int epi, int vk, int lpr, const ChunkArgs& c, const RowArgs& ra,
                           const ColArgs& ca, int nwork, hipStream_t st, const KEvents* ev = nullptr);

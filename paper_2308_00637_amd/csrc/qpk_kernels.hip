@@ -31,6 +31,27 @@ __device__ __forceinline__ float ldv(const uint16_t* p, int64_t i) {
   return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
 }
 
+typedef __attribute__((address_space(1))) void gvoid;   // global memory
+typedef __attribute__((address_space(3))) void lvoid;   // LDS
+
+// Two consecutive stored values from an even (pair-aligned) index: one 16-,
+// 8- or 4-byte load.
+__device__ __forceinline__ void ldv2(const double* p, int64_t i, double& x, double& y) {
+  const double2 v = *reinterpret_cast<const double2*>(p + i);
+  x = v.x;
+  y = v.y;
+}
+__device__ __forceinline__ void ldv2(const float* p, int64_t i, float& x, float& y) {
+  const float2 v = *reinterpret_cast<const float2*>(p + i);
+  x = v.x;
+  y = v.y;
+}
+__device__ __forceinline__ void ldv2(const uint16_t* p, int64_t i, float& x, float& y) {
+  const uint32_t u = *reinterpret_cast<const uint32_t*>(p + i);
+  x = __uint_as_float(u << 16);
+  y = __uint_as_float(u & 0xffff0000u);
+}
+
 __device__ __forceinline__ bool has_lo(double l) { return l > -INFINITY; }
 __device__ __forceinline__ bool has_hi(double u) { return u < INFINITY; }
 
@@ -386,87 +407,151 @@ __device__ double block_sum_nt(double v) {
   return r;
 }
 
-template <int EPI, int VK, int LPR>
-__global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra, ColArgs ca) {
+// Raw buffer resources: a load whose byte offset is at or past num_records
+// returns zero without touching memory, so loads past a segment's end need no
+// branch.  kOob is such an offset for every array here (all are < 2 GiB).
+constexpr uint32_t kOob = 0x80000000u;
+constexpr int kRsrcWord3 = 0x00020000;   // 32-bit data format, no swizzle
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRsrcWord3);
+}
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef int i2v __attribute__((ext_vector_type(2)));
+
+// A value pair at byte offset o (zero when o is out of range).
+__device__ __forceinline__ void ldv2b(const double*, __amdgpu_buffer_rsrc_t r, uint32_t o, double& x,
+                                      double& y) {
+  const d2v v = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+  x = v.x;
+  y = v.y;
+}
+__device__ __forceinline__ void ldv2b(const float*, __amdgpu_buffer_rsrc_t r, uint32_t o, float& x,
+                                      float& y) {
+  const f2v v = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+  x = v.x;
+  y = v.y;
+}
+__device__ __forceinline__ void ldv2b(const uint16_t*, __amdgpu_buffer_rsrc_t r, uint32_t o, float& x,
+                                      float& y) {
+  const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
+  x = __uint_as_float(u << 16);
+  y = __uint_as_float(u & 0xffff0000u);
+}
+
+// Kernel variants: KV 0 stages the chunk through registers (16-byte loads,
+// all issued at once), KV 1 with direct global-to-LDS loads (no registers
+// held, so a half-LDS chunk pass fits 64 VGPRs and two blocks share a CU).
+//
+// Every (chunk, row) segment starts at an even entry and has even length
+// (zero-padded), so a lane loads its entries in pairs: one 16-byte value load
+// (float64) and one 4-byte load of two uint16 column offsets per pair.  A
+// group of LPR lanes reduces one row; lane l takes pairs l, l + LPR, ...
+template <int EPI, int VK, int LPR, int KV>
+__device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& ra, const ColArgs& ca) {
   using T = typename VT<VK>::T;
   using Acc = typename VT<VK>::Acc;
+  constexpr bool DMA = KV == 1;
   if ((ra.done && *ra.done) || (ca.done && *ca.done)) return;
   if constexpr (EPI == CE_COL) {
     if (ca.bump && blockIdx.x == 0 && threadIdx.x == 0) *ca.bump += 1;
   }
   extern __shared__ __align__(16) double lds[];
   const int c = b.work[3 * blockIdx.x], r0 = b.work[3 * blockIdx.x + 1], r1 = b.work[3 * blockIdx.x + 2];
-  const int32_t* __restrict__ rp = b.rowptr + static_cast<int64_t>(c) * (b.nrows + 1);
-  const uint16_t* __restrict__ col = b.col;
-  const T* __restrict__ val = static_cast<const T*>(b.val);
+  const int32_t* rp = b.rowptr + static_cast<int64_t>(c) * (b.nrows + 1);
+  const T* val = static_cast<const T*>(b.val);
+  const __amdgpu_buffer_rsrc_t rrp = rsrc(rp, 4u * static_cast<uint32_t>(b.nrows + 1));
+  const __amdgpu_buffer_rsrc_t rcol = rsrc(b.col, 2u * static_cast<uint32_t>(b.nstored));
+  const __amdgpu_buffer_rsrc_t rval = rsrc(val, static_cast<uint32_t>(sizeof(T)) * b.nstored);
   const int lane = threadIdx.x & (LPR - 1);
   const int gid = threadIdx.x / LPR;
   constexpr int NG = kChunkBlock / LPR;
-  constexpr int PER = 8;                     // entries per lane per batch
-  constexpr int SPAN = LPR * PER;            // entries per group per batch
+  constexpr int PP = 4;                      // entry pairs per lane per batch
+  constexpr int SPAN = 2 * LPR * PP;         // entries per group per batch
+  using LT = decltype(ldv(val, 0));          // loaded value type
 
-  // Row bounds of this group's first row, then every staging load at once
-  // (16-byte loads), so the block waits for one memory latency, not twenty.
-  int row = r0 + gid;
-  int beg = 0, end = 0;
-  if (row < r1) {
-    beg = rp[row];
-    end = rp[row + 1];
-  }
+  // the pairs of one batch starting at entry `base` of a segment ending at `end`
+  auto load_batch = [&](int base, int end, uint32_t* cc, LT* vx, LT* vy) {
+#pragma unroll
+    for (int k = 0; k < PP; ++k) {
+      const int q = base + 2 * (lane + k * LPR);
+      const bool ok = q < end;
+      cc[k] = __builtin_amdgcn_raw_buffer_load_b32(rcol, ok ? 2u * q : kOob, 0, 0);
+      ldv2b(val, rval, ok ? static_cast<uint32_t>(sizeof(T)) * q : kOob, vx[k], vy[k]);
+    }
+  };
+  // [rowptr[r], rowptr[r + 1]) for r < r1, else an empty segment
+  auto bounds = [&](int r, int& beg, int& end) {
+    const i2v be = __builtin_bit_cast(
+        i2v, __builtin_amdgcn_raw_buffer_load_b64(rrp, r < r1 ? 4u * r : kOob, 0, 0));
+    beg = be.x;
+    end = be.y;
+  };
+
   const int c0 = c * b.chunk_cols;
   const int cw = min(b.chunk_cols, b.ncols - c0);
-  constexpr int SP = (kChunkCols + 2 * kChunkBlock - 1) / (2 * kChunkBlock);
-  const double2* __restrict__ s2 = reinterpret_cast<const double2*>(b.src + c0);
+  constexpr int SP = DMA ? 1 : (kChunkCols + 2 * kChunkBlock - 1) / (2 * kChunkBlock);
   double2 st[SP];
+  if constexpr (DMA) {
+    // wave w copies the 1 KB pieces w, w + 16, ... of the chunk, 16 bytes a lane
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const int npair = cw >> 1;
+    for (int base = wv * 64; base < npair; base += kChunkBlock) {
+      if (base + ln < npair)
+        __builtin_amdgcn_global_load_lds((gvoid*)(b.src + c0 + 2 * (base + ln)),
+                                         (lvoid*)(lds + 2 * base), 16, 0, 0);
+    }
+  } else {
+    // every staging load at once, so the block waits for one memory latency
+    const __amdgpu_buffer_rsrc_t rsv = rsrc(b.src + c0, 16u * static_cast<uint32_t>(cw >> 1));
 #pragma unroll
-  for (int k = 0; k < SP; ++k) {
-    const int i2 = threadIdx.x + k * kChunkBlock;
-    st[k] = 2 * i2 + 1 < cw ? s2[i2] : make_double2(0.0, 0.0);
+    for (int k = 0; k < SP; ++k) {
+      const uint32_t i2 = threadIdx.x + k * kChunkBlock;
+      st[k] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rsv, 16u * i2, 0, 0));
+    }
   }
-  // first batch of the first row, in flight together with the staging loads
-  int ci[PER];
-  Acc vv[PER];
+  // Software pipeline over this group's rows r0 + gid, + NG, ...: the row
+  // bounds are loaded three rows ahead and the entry batch one row ahead of
+  // the row being reduced, so no load waits on another's latency.
+  int row = r0 + gid;
+  int beg, end, b1, e1, b2, e2;
+  bounds(row, beg, end);
+  bounds(row + NG, b1, e1);
+  bounds(row + 2 * NG, b2, e2);
+  uint32_t cc[PP], cc1[PP];
+  LT vx[PP], vy[PP], vx1[PP], vy1[PP];
+  load_batch(beg, end, cc, vx, vy);
+  if constexpr (DMA) {
+    __builtin_amdgcn_s_waitcnt(0);   // LDS-direct loads are counted as vector loads
+  } else {
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int q = beg + lane + k * LPR;
-    const bool ok = q < end;
-    ci[k] = ok ? static_cast<int>(col[q]) : 0;
-    vv[k] = ok ? ldv(val, q) : Acc(0);
-  }
-#pragma unroll
-  for (int k = 0; k < SP; ++k) {
-    const int i2 = threadIdx.x + k * kChunkBlock;
-    if (2 * i2 + 1 < cw) reinterpret_cast<double2*>(lds)[i2] = st[k];
+    for (int k = 0; k < SP; ++k) {
+      const int i2 = threadIdx.x + k * kChunkBlock;
+      if (2 * i2 + 1 < cw) reinterpret_cast<double2*>(lds)[i2] = st[k];
+    }
   }
   if ((cw & 1) && threadIdx.x == 0) lds[cw - 1] = b.src[c0 + cw - 1];
   __syncthreads();
 
   double acc0 = 0.0;
   for (; row < r1; row += NG) {
-    // next row: bounds and first batch issued before this row is reduced
-    const int nrow = row + NG;
-    int nbeg = 0, nend = 0;
-    if (nrow < r1) {
-      nbeg = rp[nrow];
-      nend = rp[nrow + 1];
-    }
-    int nci[PER];
-    Acc nvv[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int q = nbeg + lane + k * LPR;
-      const bool ok = q < nend;
-      nci[k] = ok ? static_cast<int>(col[q]) : 0;
-      nvv[k] = ok ? ldv(val, q) : Acc(0);
-    }
+    int b3, e3;
+    bounds(row + 3 * NG, b3, e3);
+    load_batch(b1, e1, cc1, vx1, vy1);
     Acc t = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) t += vv[k] * static_cast<Acc>(lds[ci[k]]);
+    for (int k = 0; k < PP; ++k) {
+      t += static_cast<Acc>(vx[k]) * static_cast<Acc>(lds[cc[k] & 0xffffu]);
+      t += static_cast<Acc>(vy[k]) * static_cast<Acc>(lds[cc[k] >> 16]);
+    }
     for (int base = beg + SPAN; base < end; base += SPAN) {   // rows longer than one batch
+      uint32_t c2[PP];
+      LT x[PP], y[PP];
+      load_batch(base, end, c2, x, y);
 #pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int q = base + lane + k * LPR;
-        if (q < end) t += ldv(val, q) * static_cast<Acc>(lds[col[q]]);
+      for (int k = 0; k < PP; ++k) {
+        t += static_cast<Acc>(x[k]) * static_cast<Acc>(lds[c2[k] & 0xffffu]);
+        t += static_cast<Acc>(y[k]) * static_cast<Acc>(lds[c2[k] >> 16]);
       }
     }
     t = group_sum<LPR>(t);
@@ -476,12 +561,17 @@ __global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra
       else if constexpr (EPI == CE_ROW) acc0 += row_matvec_epilogue(ra, row, td);
       else acc0 += col_matvec_epilogue(ca, row, td);
     }
-    beg = nbeg;
-    end = nend;
+    beg = b1;
+    end = e1;
+    b1 = b2;
+    e1 = e2;
+    b2 = b3;
+    e2 = e3;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      ci[k] = nci[k];
-      vv[k] = nvv[k];
+    for (int k = 0; k < PP; ++k) {
+      cc[k] = cc1[k];
+      vx[k] = vx1[k];
+      vy[k] = vy1[k];
     }
   }
   if constexpr (EPI != CE_PARTIAL) {
@@ -491,6 +581,18 @@ __global__ __launch_bounds__(kChunkBlock) void k_chunked(ChunkArgs b, RowArgs ra
       else ca.part0[blockIdx.x] = acc0;
     }
   }
+}
+
+// Waves per SIMD the compiler must leave room for: a multi-chunk pass without
+// register staging is held to 64 VGPRs so two 1024-thread blocks share a CU.
+template <int EPI, int KV>
+constexpr int chunked_min_waves() { return (EPI == CE_PARTIAL && KV == 1) ? 8 : 1; }
+
+template <int EPI, int VK, int LPR, int KV>
+__global__ __launch_bounds__(kChunkBlock)
+__attribute__((amdgpu_waves_per_eu(chunked_min_waves<EPI, KV>())))
+void k_chunked(ChunkArgs b, RowArgs ra, ColArgs ca) {
+  chunked_body<EPI, VK, LPR, KV>(b, ra, ca);
 }
 
 // Sum of the per-chunk partials in chunk order, then the matvec epilogue.
@@ -1043,18 +1145,33 @@ hipError_t launch_colpass(int mode, int vk, int lpr, const ColArgs& a, int grid,
   }
 }
 
+template <int EPI, int VK, int KV>
+static hipError_t chunked_lpr_kv(int lpr, const ChunkArgs& c, const RowArgs& ra, const ColArgs& ca,
+                                 int nwork, hipStream_t st, const KEvents* ev) {
+  const size_t lds = sizeof(double) * c.chunk_cols;
+  const dim3 g(nwork), bl(kChunkBlock);
+  switch (lpr) {
+    case 4: return launch_ev(ev, k_chunked<EPI, VK, 4, KV>, g, bl, lds, st, c, ra, ca);
+    case 8: return launch_ev(ev, k_chunked<EPI, VK, 8, KV>, g, bl, lds, st, c, ra, ca);
+    case 16: return launch_ev(ev, k_chunked<EPI, VK, 16, KV>, g, bl, lds, st, c, ra, ca);
+    case 32: return launch_ev(ev, k_chunked<EPI, VK, 32, KV>, g, bl, lds, st, c, ra, ca);
+    default: return launch_ev(ev, k_chunked<EPI, VK, 64, KV>, g, bl, lds, st, c, ra, ca);
+  }
+}
+
+// float64 row-side and multi-chunk passes come in both staging variants; the
+// others use kKvDefault.
+template <int EPI, int VK>
+constexpr bool kv_all() { return VK == VK_F64 && EPI != CE_COL; }
+
 template <int EPI, int VK>
 static hipError_t chunked_lpr(int lpr, const ChunkArgs& c, const RowArgs& ra, const ColArgs& ca,
                               int nwork, hipStream_t st, const KEvents* ev) {
-  const size_t lds = sizeof(double) * c.chunk_cols;
-  switch (lpr) {
-    case 4: return launch_ev(ev, k_chunked<EPI, VK, 4>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
-    case 8: return launch_ev(ev, k_chunked<EPI, VK, 8>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
-    case 16: return launch_ev(ev, k_chunked<EPI, VK, 16>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
-    case 32: return launch_ev(ev, k_chunked<EPI, VK, 32>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
-    default: return launch_ev(ev, k_chunked<EPI, VK, 64>, dim3(nwork), dim3(kChunkBlock), lds, st, c, ra, ca);
+  if constexpr (kv_all<EPI, VK>()) {
+    if (c.kv == 0) return chunked_lpr_kv<EPI, VK, 0>(lpr, c, ra, ca, nwork, st, ev);
+    return chunked_lpr_kv<EPI, VK, 1>(lpr, c, ra, ca, nwork, st, ev);
   }
-  return hipGetLastError();
+  return chunked_lpr_kv<EPI, VK, kKvDefault>(lpr, c, ra, ca, nwork, st, ev);
 }
 
 template <int EPI>
@@ -1074,19 +1191,29 @@ hipError_t launch_chunked(int epi, int vk, int lpr, const ChunkArgs& c, const Ro
   return chunked_vk<CE_PARTIAL>(vk, lpr, c, ra, ca, nwork, st, ev);
 }
 
-template <int EPI, int VK>
-static hipError_t set_attr_lpr() {
+template <int EPI, int VK, int KV>
+static hipError_t set_attr_kv() {
   const int lds = sizeof(double) * kChunkCols;
   hipError_t e = hipSuccess;
   auto one = [&](const void* f) {
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   };
-  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 4>));
-  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 8>));
-  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 16>));
-  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 32>));
-  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 64>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 4, KV>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 8, KV>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 16, KV>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 32, KV>));
+  one(reinterpret_cast<const void*>(&k_chunked<EPI, VK, 64, KV>));
   return e;
+}
+
+template <int EPI, int VK>
+static hipError_t set_attr_lpr() {
+  if constexpr (kv_all<EPI, VK>()) {
+    hipError_t e = set_attr_kv<EPI, VK, 0>();
+    if (e == hipSuccess) e = set_attr_kv<EPI, VK, 1>();
+    return e;
+  }
+  return set_attr_kv<EPI, VK, kKvDefault>();
 }
 
 hipError_t chunked_set_attributes() {
