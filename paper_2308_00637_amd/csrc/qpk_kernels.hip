@@ -107,6 +107,40 @@ __device__ double sum_bcast(const double* p, int cnt) {
   return v;
 }
 
+// Three block-wide sums of per-block partials, broadcast to every thread.
+// Each sum runs in the same order as sum_bcast (thread-strided, then the block
+// tree), so the results are bitwise those of three sum_bcast calls; the three
+// partial arrays are read together, so the block waits for one latency.
+__device__ void sum3_bcast(const double* p0, int c0, const double* p1, int c1, const double* p2,
+                           int c2, double& s0, double& s1, double& s2) {
+  __shared__ double sh[3][kBlock / 64];
+  __shared__ double out[3];
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int i = threadIdx.x; i < c0; i += kBlock) v0 += p0[i];
+  for (int i = threadIdx.x; i < c1; i += kBlock) v1 += p1[i];
+  for (int i = threadIdx.x; i < c2; i += kBlock) v2 += p2[i];
+  v0 = group_sum<64>(v0);
+  v1 = group_sum<64>(v1);
+  v2 = group_sum<64>(v2);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = v0;
+    sh[1][w] = v1;
+    sh[2][w] = v2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) r += sh[threadIdx.x][i];
+    out[threadIdx.x] = r;
+  }
+  __syncthreads();
+  s0 = out[0];
+  s1 = out[1];
+  s2 = out[2];
+}
+
 __device__ double min_bcast(const double* p, int cnt) {
   __shared__ double shb;
   double v = INFINITY;
@@ -596,15 +630,29 @@ void k_chunked(ChunkArgs b, RowArgs ra, ColArgs ca) {
 }
 
 // Sum of the per-chunk partials in chunk order, then the matvec epilogue.
+// Partials of row r in chunk order, eight loads in flight at a time.
+__device__ __forceinline__ double sum_partials(const ChunkArgs& b, int r) {
+  const double* p = b.partial + r;
+  const int64_t st = b.nrows;
+  double y = 0.0;
+  int c = 0;
+  for (; c + 8 <= b.nchunk; c += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(c + u) * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y += t[u];
+  }
+  for (; c < b.nchunk; ++c) y += p[c * st];
+  return y;
+}
+
 __global__ __launch_bounds__(kBlock) void k_chunk_epilogue_col(ChunkArgs b, ColArgs a) {
   if (a.done && *a.done) return;
   if (a.bump && blockIdx.x == 0 && threadIdx.x == 0) *a.bump += 1;
   double acc0 = 0.0;
-  for (int j = blockIdx.x * kBlock + threadIdx.x; j < b.nrows; j += gridDim.x * kBlock) {
-    double y = 0.0;
-    for (int c = 0; c < b.nchunk; ++c) y += b.partial[static_cast<int64_t>(c) * b.nrows + j];
-    acc0 += col_matvec_epilogue(a, j, y);
-  }
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < b.nrows; j += gridDim.x * kBlock)
+    acc0 += col_matvec_epilogue(a, j, sum_partials(b, j));
   acc0 = block_sum(acc0);
   if (threadIdx.x == 0) a.part0[blockIdx.x] = acc0;
 }
@@ -612,11 +660,8 @@ __global__ __launch_bounds__(kBlock) void k_chunk_epilogue_col(ChunkArgs b, ColA
 __global__ __launch_bounds__(kBlock) void k_chunk_epilogue_row(ChunkArgs b, RowArgs a) {
   if (a.done && *a.done) return;
   double acc0 = 0.0;
-  for (int r = blockIdx.x * kBlock + threadIdx.x; r < b.nrows; r += gridDim.x * kBlock) {
-    double t = 0.0;
-    for (int c = 0; c < b.nchunk; ++c) t += b.partial[static_cast<int64_t>(c) * b.nrows + r];
-    acc0 += row_matvec_epilogue(a, r, t);
-  }
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < b.nrows; r += gridDim.x * kBlock)
+    acc0 += row_matvec_epilogue(a, r, sum_partials(b, r));
   acc0 = block_sum(acc0);
   if (threadIdx.x == 0) a.part0[blockIdx.x] = acc0;
 }
@@ -923,13 +968,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgArgs a) {
   }
 }
 
+// The vector loads of a thread's first element are issued before the
+// partial sums are read, so the two memory latencies overlap.
 __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
+  const int stride = gridDim.x * kBlock;
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0, di = 1.0;
+  if (i < a.N) {
+    xi = a.x[i];
+    pi = a.p[i];
+    ri = a.r[i];
+    qi = a.q[i];
+    di = a.jdiag[i];
+  }
   if (a.fl[F_DONE]) return;
   const int k = a.fl[F_CNT];
   const double* P = a.part;
-  double pq = sum_bcast(P + P_DOT_R * kGridMax, a.g_r) + sum_bcast(P + P_DOT_X * kGridMax, a.g_x);
+  double pqr, pqx, rz;
+  sum3_bcast(P + P_DOT_R * kGridMax, a.g_r, P + P_DOT_X * kGridMax, a.g_x,
+             P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec, pqr, pqx, rz);
+  double pq = pqr + pqx;
   if (a.has_ts) pq += P[P_DOT_TS * kGridMax];
-  const double rz = sum_bcast(P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec);
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.fl[F_STATUS] = (isfinite(pq) && isfinite(rz)) ? QP_ERR_NOT_SPD_CODE : QP_ERR_NUMERIC_CODE;
@@ -940,14 +999,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
   }
   const double alpha = rz / pq;
   double rzn = 0.0, rr = 0.0;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock) {
-    a.x[i] += alpha * a.p[i];
-    const double r = a.r[i] - alpha * a.q[i];
-    const double z = r / a.jdiag[i];
+  for (; i < a.N; i += stride) {
+    a.x[i] = xi + alpha * pi;
+    const double r = ri - alpha * qi;
+    const double z = r / di;
     a.r[i] = r;
     a.z[i] = z;
     rzn += r * z;
     rr += r * r;
+    const int j = i + stride;
+    if (j < a.N) {
+      xi = a.x[j];
+      pi = a.p[j];
+      ri = a.r[j];
+      qi = a.q[j];
+      di = a.jdiag[j];
+    }
   }
   rzn = block_sum(rzn);
   rr = block_sum(rr);
@@ -958,12 +1025,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_pupdate(CgArgs a) {
+  const int stride = gridDim.x * kBlock;
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  double zi = 0.0, pi = 0.0;
+  if (i < a.N) {
+    zi = a.z[i];
+    pi = a.p[i];
+  }
   if (a.fl[F_DONE]) return;
   const int k = a.fl[F_CNT];
   const double* P = a.part;
-  const double rz_old = sum_bcast(P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec);
-  const double rz_new = sum_bcast(P + (((k + 1) & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec);
-  const double rr = sum_bcast(P + P_RR * kGridMax, a.g_vec);
+  double rz_old, rz_new, rr;
+  sum3_bcast(P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec,
+             P + (((k + 1) & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec, P + P_RR * kGridMax, a.g_vec,
+             rz_old, rz_new, rr);
   const bool conv = sqrt(rr) <= a.tol * a.sc[S_RHSNORM];
   if (conv || k + 1 >= a.maxit) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -974,8 +1049,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(CgArgs a) {
     return;
   }
   const double beta = rz_new / rz_old;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.N; i += gridDim.x * kBlock)
-    a.p[i] = a.z[i] + beta * a.p[i];
+  for (; i < a.N; i += stride) {
+    a.p[i] = zi + beta * pi;
+    const int j = i + stride;
+    if (j < a.N) {
+      zi = a.z[j];
+      pi = a.p[j];
+    }
+  }
 }
 
 // Residual replacement for the reduced-precision operator (the reliable-update
