@@ -71,6 +71,8 @@ struct qp_handle_s {
   } ck_r, ck_x;
   int g_rmv = 1, g_xmv = 1;             // partial counts of the PCG matvec passes
   int g_epi_r = 1, g_epi_x = 1;          // grids of the chunk epilogues
+  bool alternate = true;                 // alternate the row direction of the blocked passes
+  int64_t n_matvec = 0;                  // blocked K v products so far
   double* uw = nullptr;  // [u (p_rows) | wA (m)] for the PCG matvec
   std::vector<void*> allocs;
   // optional event timing of PCG launches
@@ -284,8 +286,9 @@ static qp_status prepare(qp_handle h) {
   return QP_OK;
 }
 
-static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double* src) {
+static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double* src, bool reverse) {
   ChunkArgs c{};
+  c.reverse = reverse ? 1 : 0;
   c.nrows = k.nrows; c.ncols = k.ncols; c.nchunk = k.nchunk; c.chunk_cols = k.chunk_cols;
   c.work = k.work; c.rowptr = k.rowptr; c.col = k.col;
   c.val = lo ? k.val_lo : (const void*)k.val;
@@ -301,6 +304,7 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
                             int* bump) {
   const int vk = lo ? h->vk : VK_F64;
   const bool prof = bump != nullptr;  // only the PCG iteration's own matvec is timed
+  const bool rev = h->alternate && (h->n_matvec++ & 1);
   if (reinterpret_cast<uintptr_t>(v) & 15) {
     // the blocked row pass stages v with 16-byte loads
     HIPCHK(launch_copy(v, h->valign, h->N(), 1.0, h->st));
@@ -326,7 +330,7 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
     const KEvents ev = prof_slot(h, QP_PROF_ROWPASS, prof);
     if (h->ck_r.on) {
-      ChunkArgs ca = chunk_args(h->ck_r, lo, v);
+      ChunkArgs ca = chunk_args(h->ck_r, lo, v, rev);
       if (h->ck_r.nchunk == 1) {
         HIPCHK(launch_chunked(CE_ROW, vk, h->ck_r.lpr, ca, a, ColArgs{}, h->ck_r.nwork, h->st, &ev));
       } else {
@@ -344,7 +348,7 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
   c.part0 = h->part + P_DOT_X * kGridMax; c.done = done; c.bump = bump;
   const KEvents ev = prof_slot(h, QP_PROF_COLPASS, prof);
   if (h->ck_x.on) {
-    ChunkArgs ca = chunk_args(h->ck_x, lo, h->uw);
+    ChunkArgs ca = chunk_args(h->ck_x, lo, h->uw, rev);
     if (h->ck_x.nchunk == 1) {
       HIPCHK(launch_chunked(CE_COL, vk, h->ck_x.lpr, ca, RowArgs{}, c, h->ck_x.nwork, h->st, &ev));
     } else {
@@ -880,6 +884,7 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   if (want_ck_x)
     CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1,
                       "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
+  if (const char* e = std::getenv("QPK_ALTERNATE")) h->alternate = std::atoi(e) != 0;
   h->g_epi_r = grid_cap(std::max<int64_t>(h->nRP, 1), kBlock, kGridMax);
   h->g_epi_x = grid_cap(n, kBlock, kGridMax);
   if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi_r;

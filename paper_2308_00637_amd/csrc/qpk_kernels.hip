@@ -515,9 +515,15 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
     }
   };
   // [rowptr[r], rowptr[r + 1]) for r < r1, else an empty segment
-  auto bounds = [&](int r, int& beg, int& end) {
+  // This group's rows are r0 + gid + k NG, k = 0 .. nk-1, visited in that order
+  // or (b.reverse) mirrored within [r0, r1), last row first.  Alternating the
+  // direction between passes starts each pass on the data the previous pass
+  // over the same operator touched last, which the memory-side cache still holds.
+  const int nk = r1 - r0 > gid ? (r1 - r0 - gid + NG - 1) / NG : 0;
+  auto row_of = [&](int k) { return b.reverse ? r1 - 1 - gid - k * NG : r0 + gid + k * NG; };
+  auto bounds = [&](int k, int& beg, int& end) {
     const i2v be = __builtin_bit_cast(
-        i2v, __builtin_amdgcn_raw_buffer_load_b64(rrp, r < r1 ? 4u * r : kOob, 0, 0));
+        i2v, __builtin_amdgcn_raw_buffer_load_b64(rrp, k < nk ? 4u * row_of(k) : kOob, 0, 0));
     beg = be.x;
     end = be.y;
   };
@@ -547,11 +553,10 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
   // Software pipeline over this group's rows r0 + gid, + NG, ...: the row
   // bounds are loaded three rows ahead and the entry batch one row ahead of
   // the row being reduced, so no load waits on another's latency.
-  int row = r0 + gid;
   int beg, end, b1, e1, b2, e2;
-  bounds(row, beg, end);
-  bounds(row + NG, b1, e1);
-  bounds(row + 2 * NG, b2, e2);
+  bounds(0, beg, end);
+  bounds(1, b1, e1);
+  bounds(2, b2, e2);
   uint32_t cc[PP], cc1[PP];
   LT vx[PP], vy[PP], vx1[PP], vy1[PP];
   load_batch(beg, end, cc, vx, vy);
@@ -568,9 +573,10 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
   __syncthreads();
 
   double acc0 = 0.0;
-  for (; row < r1; row += NG) {
+  for (int kr = 0; kr < nk; ++kr) {
+    const int row = row_of(kr);
     int b3, e3;
-    bounds(row + 3 * NG, b3, e3);
+    bounds(kr + 3, b3, e3);
     load_batch(b1, e1, cc1, vx1, vy1);
     Acc t = 0;
 #pragma unroll
