@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the per-kernel HBM traffic summary of two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) and exit; needs --bench-json")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
+                    help="print per-kernel means of every counter in rocprofv3 --pmc "
+                         "counter_collection.csv files and exit; needs --bench-json")
     ap.add_argument("--bench-json", help="the JSON line printed by the profiled bench run")
     ap.add_argument("--command", default="", help="the profiled command, quoted in the summary")
     return ap.parse_args()
@@ -145,14 +148,9 @@ def summarize_stats(path, command):
     print("\n".join(out))
 
 
-def summarize_counters(fetch_csv, write_csv, bench_json, command):
-    """Per-category FETCH_SIZE / WRITE_SIZE (KiB per dispatch), the factors that
-    map each counter onto the bytes of the bench's plain device copy, and the
-    machine-readable line the bench reads back (keyed to the kernel sources)."""
-    import csv
-    rec = json.loads([ln for ln in open(bench_json) if ln.startswith("{")][-1])
-    lay = rec["layout"]
-    calib = rec["copy_calibration_bytes"]
+def kernel_category(lay):
+    """Maps a rocprofv3 record to the bench's kernel category (None for the
+    kernels outside the PCG iteration)."""
     grid = {"row": lay["row"]["work_items"], "col": lay["col"]["work_items"]}
 
     def category(r):
@@ -175,6 +173,38 @@ def summarize_counters(fetch_csv, write_csv, bench_json, command):
         if name in ("k_cg_update", "k_cg_pupdate"):
             return name.replace("k_", "")
         return None
+
+    return category
+
+
+def summarize_pmc(paths, bench_json, command):
+    import csv
+    rec = json.loads([ln for ln in open(bench_json) if ln.startswith("{")][-1])
+    category = kernel_category(rec["layout"])
+    agg = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            c = category(r)
+            if c:
+                agg.setdefault(c, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    names = sorted({n for v in agg.values() for n in v})
+    out = ["# rocprofv3 counters per PCG kernel (mean per dispatch)", "",
+           f"Command (one run per counter set): `{command}`", "",
+           "| counter | " + " | ".join(agg) + " |", "|---|" + "---|" * len(agg)]
+    for n in names:
+        out.append(f"| {n} | " + " | ".join(
+            f"{sum(agg[c][n]) / len(agg[c][n]):.4g}" if n in agg[c] else "" for c in agg) + " |")
+    print("\n".join(out))
+
+
+def summarize_counters(fetch_csv, write_csv, bench_json, command):
+    """Per-category FETCH_SIZE / WRITE_SIZE (KiB per dispatch), the factors that
+    map each counter onto the bytes of the bench's plain device copy, and the
+    machine-readable line the bench reads back (keyed to the kernel sources)."""
+    import csv
+    rec = json.loads([ln for ln in open(bench_json) if ln.startswith("{")][-1])
+    calib = rec["copy_calibration_bytes"]
+    category = kernel_category(rec["layout"])
 
     def load(path, counter):
         per, copy = {}, 0.0
@@ -243,6 +273,9 @@ def main():
     args = parse()
     if args.summarize_stats:
         summarize_stats(args.summarize_stats, args.command)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.bench_json, args.command)
         return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, args.bench_json, args.command)
