@@ -83,18 +83,21 @@ def kernel_bytes(spec, ob, lay, cat, prec_bytes):
     col_out = 8 * n * 3 + 8 * n * me                       # p_x, qdiag, q_x out, C
     row_multi = lay["row"]["chunks"] > 1
     col_multi = lay["col"]["chunks"] > 1
+    # PCG products on a multi-chunk column side leave its epilogue to the CG
+    # update; the column pass then also reads p_x and diag(H) for p.q
+    col_fused = col_multi and lay["col"]["work_items"] <= 2048
     if cat == "rowpass":
         return ob["row_bytes"] + 8 * n + (0 if row_multi else row_out)
     if cat == "colpass":
         return (ob["col_bytes"] + n * k * prec_bytes + 8 * p_rows + 8 * m
-                + (0 if col_multi else col_out))
+                + (16 * n if col_fused else 0 if col_multi else col_out))
     if cat == "epilogue":
         sides = [b for b, on in ((row_out, row_multi), (col_out, col_multi)) if on]
         return sum(sides) / max(1, len(sides))
     if cat == "tsreduce":
         return n * k * prec_bytes + 8 * n * (1 + me)
-    if cat == "cg_update":
-        return 8 * 8 * N          # x, p, r, q, diag in; x, r, z out
+    if cat == "cg_update":     # x, p, r, q, diag in; x, r, z out (fused: q_x from partials, diag(H) in)
+        return 8 * 8 * N + (8 * n * me + 8 * n if col_fused else 0)
     if cat == "cg_pupdate":
         return 3 * 8 * N          # z, p in; p out
     return 0

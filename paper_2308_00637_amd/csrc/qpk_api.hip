@@ -298,10 +298,19 @@ static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double
   return c;
 }
 
+// True when a PCG product leaves the column epilogue to k_cg_update: the
+// column side has several chunks (so an epilogue), and the single-chunk row
+// pass can form all of p.q from its row terms and a slice of the diagonal.
+static bool pcg_fuses_epilogue(qp_handle h) {
+  return h->ck_x.on && h->ck_x.nchunk > 1 && h->ck_r.on && h->ck_r.nchunk == 1 && h->nRP > 0;
+}
+
 // Step a4: y = K v (v, y: K-vectors).  lo selects the reduced-precision
-// operator copies.  done/bump: PCG early exit and iteration counter.
+// operator copies.  done/bump: PCG early exit and iteration counter.  fuse
+// (PCG iterations only, when pcg_fuses_epilogue): the x-part of y is left as
+// per-chunk partials, and the row pass's partials carry all of p.q.
 static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, const int* done,
-                            int* bump) {
+                            int* bump, bool fuse = false) {
   const int vk = lo ? h->vk : VK_F64;
   const bool prof = bump != nullptr;  // only the PCG iteration's own matvec is timed
   const bool rev = h->alternate && (h->n_matvec++ & 1);
@@ -328,6 +337,12 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     a.vl = h->m > 0 ? v + h->n : v;
     a.dl = h->dl; a.yl = y + h->n;
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
+    if (fuse && pcg_fuses_epilogue(h)) {
+      a.xdot = 1;
+      a.qdiag = h->qdiag;
+      a.Cm = h->Cm;
+      a.we = h->we_mv;
+    }
     const KEvents ev = prof_slot(h, QP_PROF_ROWPASS, prof);
     if (h->ck_r.on) {
       ChunkArgs ca = chunk_args(h->ck_r, lo, v, rev);
@@ -351,6 +366,9 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     ChunkArgs ca = chunk_args(h->ck_x, lo, h->uw, rev);
     if (h->ck_x.nchunk == 1) {
       HIPCHK(launch_chunked(CE_COL, vk, h->ck_x.lpr, ca, RowArgs{}, c, h->ck_x.nwork, h->st, &ev));
+    } else if (fuse && pcg_fuses_epilogue(h)) {
+      HIPCHK(launch_chunked(CE_PARTIAL, vk, h->ck_x.lpr, ca, RowArgs{}, c, h->ck_x.nwork, h->st,
+                            &ev));
     } else {
       ColArgs c0 = c;
       c0.bump = nullptr;
@@ -395,6 +413,17 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
                          pcg_info* info, bool force64 = false) {
   CgArgs a = cg_args(h, rhs, sol, o);
   HIPCHK(launch_cg_init(a, h->st));
+  const bool fuse = pcg_fuses_epilogue(h);
+  CgArgs au = a;   // k_cg_update's view: q's x-part from the column partials
+  if (fuse) {
+    au.qpart = h->ck_x.partial;
+    au.nchunk = h->ck_x.nchunk;
+    au.g_x = 0;   // p.q is all in the row pass's partials
+    au.me = h->me;
+    au.qdiag = h->qdiag;
+    au.Cm = h->Cm;
+    au.we = h->we_mv;
+  }
   const bool lo = h->vk != VK_F64 && !force64;
   const int check = std::max(1, o.check_every);
   int it = 0;
@@ -410,9 +439,9 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
           CHK(run_matvec(h, false, sol, h->tmp, h->fl + F_DONE, nullptr));
           HIPCHK(launch_cg_restart(a, h->tmp, 0, h->st));
         }
-        CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT));
+        CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT, fuse));
         const KEvents e1 = prof_slot(h, QP_PROF_CGUPDATE, true);
-        HIPCHK(launch_cg_update(a, h->st, &e1));
+        HIPCHK(launch_cg_update(au, h->st, &e1));
         const KEvents e2 = prof_slot(h, QP_PROF_CGPUPDATE, true);
         HIPCHK(launch_cg_pupdate(a, h->st, &e2));
       }

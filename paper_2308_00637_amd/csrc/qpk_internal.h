@@ -71,6 +71,12 @@ struct RowArgs {
   double* gw;                // R_GRADW output
   const int* done;           // optional early-exit flag (PCG)
   int* bump;                 // optional PCG iteration counter to advance
+  // R_MATVEC / CE_ROW: also accumulate v_x . (K v)_x into part0 (the column
+  // pass then leaves its x-part unsummed; see CgArgs::qpart)
+  int32_t xdot;
+  const double* qdiag;       // n
+  const double* Cm;          // me*n row-major
+  const double* we;          // me
 };
 
 struct ColArgs {
@@ -275,6 +281,14 @@ struct CgArgs {
   int g_r, g_x, has_ts;      // partial counts of the matvec passes
   double tol;
   int maxit;
+  // Column epilogue folded into the update: when qpart is set, the x-part of
+  // q is summed here from the column pass's per-chunk partials (nchunk x n),
+  // plus the equality and diagonal terms, instead of being read from q.
+  const double* qpart;
+  int nchunk, me;
+  const double* qdiag;
+  const double* Cm;
+  const double* we;
 };
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t st);
 hipError_t launch_cg_update(const CgArgs& a, hipStream_t st, const KEvents* ev = nullptr);

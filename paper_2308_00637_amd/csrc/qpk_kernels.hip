@@ -398,10 +398,13 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
 // Matvec epilogues shared by the PCG passes.
 // Row epilogue of the PCG matvec (R_MATVEC): P rows give u = w t; A rows give
 // the lam-part of K v and wA = w_l - w_u.  Returns the row's p_lam . q_lam.
+// Returns this row's term of v_lam . (K v)_lam, plus with a.xdot its term of
+// v_x . (K v)_x: v_x . P^T u = sum_v t_v u_v and v_x . A^T wA = sum_i t_i wA_i.
 __device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row, double td) {
   if (row < a.p_rows) {
-    a.u[row] = a.w[row] * td;
-    return 0.0;
+    const double uv = a.w[row] * td;
+    a.u[row] = uv;
+    return a.xdot ? td * uv : 0.0;
   }
   const int i = row - a.p_rows, me = a.me, m = a.m;
   const bool hl = has_lo(a.lA[i]), hu = has_hi(a.uA[i]);
@@ -411,8 +414,9 @@ __device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row,
   const double yup = (hu ? -td : 0.0) + dup * vup;
   a.yl[me + i] = ylo;
   a.yl[me + m + i] = yup;
-  a.wA[i] = (hl ? 2.0 * td / dlo + vlo : 0.0) - (hu ? -2.0 * td / dup + vup : 0.0);
-  return vlo * ylo + vup * yup;
+  const double wa = (hl ? 2.0 * td / dlo + vlo : 0.0) - (hu ? -2.0 * td / dup + vup : 0.0);
+  a.wA[i] = wa;
+  return vlo * ylo + vup * yup + (a.xdot ? td * wa : 0.0);
 }
 
 // Column epilogue of the PCG matvec (X_MATVEC); returns v_j y_j.
@@ -487,7 +491,7 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
   using Acc = typename VT<VK>::Acc;
   constexpr bool DMA = KV == 1;
   if ((ra.done && *ra.done) || (ca.done && *ca.done)) return;
-  if constexpr (EPI == CE_COL) {
+  if constexpr (EPI != CE_ROW) {
     if (ca.bump && blockIdx.x == 0 && threadIdx.x == 0) *ca.bump += 1;
   }
   extern __shared__ __align__(16) double lds[];
@@ -597,8 +601,9 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
     t = group_sum<LPR>(t);
     if (lane == 0) {
       const double td = static_cast<double>(t);
-      if constexpr (EPI == CE_PARTIAL) b.partial[static_cast<int64_t>(c) * b.nrows + row] = td;
-      else if constexpr (EPI == CE_ROW) acc0 += row_matvec_epilogue(ra, row, td);
+      if constexpr (EPI == CE_PARTIAL) {
+        b.partial[static_cast<int64_t>(c) * b.nrows + row] = td;
+      } else if constexpr (EPI == CE_ROW) acc0 += row_matvec_epilogue(ra, row, td);
       else acc0 += col_matvec_epilogue(ca, row, td);
     }
     beg = b1;
@@ -612,6 +617,18 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
       cc[k] = cc1[k];
       vx[k] = vx1[k];
       vy[k] = vy1[k];
+    }
+  }
+  // ra.xdot: the terms of v_x . (K v)_x that are not row terms (equality rows,
+  // diagonal), block b taking the b-th slice of x; v_x is the staged chunk
+  if (EPI == CE_ROW && ra.xdot) {
+    const int j0 = static_cast<int>(static_cast<int64_t>(ra.n) * blockIdx.x / gridDim.x);
+    const int j1 = static_cast<int>(static_cast<int64_t>(ra.n) * (blockIdx.x + 1) / gridDim.x);
+    for (int j = j0 + threadIdx.x; j < j1; j += kChunkBlock) {
+      const double vj = lds[j];
+      double e = 0.0;
+      for (int i = 0; i < ra.me; ++i) e += ra.Cm[static_cast<int64_t>(i) * ra.n + j] * ra.we[i];
+      acc0 += vj * e + ra.qdiag[j] * vj * vj;
     }
   }
   if constexpr (EPI != CE_PARTIAL) {
@@ -976,6 +993,30 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgArgs a) {
 
 // The vector loads of a thread's first element are issued before the
 // partial sums are read, so the two memory latencies overlap.
+// q_i of the PCG product: read from q, or for the x-part summed from the
+// column pass's chunk partials in chunk order with the equality and diagonal
+// terms added exactly as the column epilogue adds them (so q is bitwise the
+// same either way).  Up to 32 partial loads are issued at once.
+__device__ __forceinline__ double cg_q(const CgArgs& a, int i, double pi) {
+  if (!a.qpart || i >= a.n) return a.q[i];
+  const double* p = a.qpart + i;
+  const int64_t st = a.n;
+  double y = 0.0;
+  if (a.nchunk <= 32) {
+    double t[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) t[c] = c < a.nchunk ? p[c * st] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      if (c < a.nchunk) y += t[c];
+  } else {
+    for (int c = 0; c < a.nchunk; ++c) y += p[c * st];
+  }
+  for (int e = 0; e < a.me; ++e) y += a.Cm[static_cast<int64_t>(e) * a.n + i] * a.we[e];
+  y += a.qdiag[i] * pi;
+  return y;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
   const int stride = gridDim.x * kBlock;
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -984,8 +1025,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     xi = a.x[i];
     pi = a.p[i];
     ri = a.r[i];
-    qi = a.q[i];
     di = a.jdiag[i];
+    qi = cg_q(a, i, pi);
   }
   if (a.fl[F_DONE]) return;
   const int k = a.fl[F_CNT];
@@ -1018,8 +1059,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
       xi = a.x[j];
       pi = a.p[j];
       ri = a.r[j];
-      qi = a.q[j];
       di = a.jdiag[j];
+      qi = cg_q(a, j, pi);
     }
   }
   rzn = block_sum(rzn);
