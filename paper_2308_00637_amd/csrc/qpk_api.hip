@@ -55,6 +55,8 @@ struct qp_handle_s {
   int* fl = nullptr;
   double* hsc = nullptr;  // pinned host copy of sc
   int* hfl = nullptr;     // pinned host copy of fl
+  int* hpoll = nullptr;   // pinned, 2 x F_COUNT: flag snapshots of the PCG poll
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   int lpr_r = 16, lpr_x = 64, g_r = 1, g_x = 1, g_vec = 1, g_ts = 1, ts_chunk = 1, g_n = 1, g_ra = 1;
   // LDS-staged blocked PCG matvec passes
   struct Chunked {
@@ -90,6 +92,9 @@ struct qp_handle_s {
     for (void* p : allocs) (void)hipFree(p);
     if (hsc) (void)hipHostFree(hsc);
     if (hfl) (void)hipHostFree(hfl);
+    if (hpoll) (void)hipHostFree(hpoll);
+    for (hipEvent_t e : poll_ev)
+      if (e) (void)hipEventDestroy(e);
   }
   int64_t N() const { return (int64_t)n + me + 2 * (int64_t)m; }
   int64_t nlam() const { return (int64_t)me + 2 * (int64_t)m + 2 * (int64_t)n; }
@@ -431,6 +436,11 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
   bool done = h->hfl[F_DONE] != 0;
   const double rhsn = h->hsc[S_RHSNORM];
   while (it < o.maxit) {
+    // The stop flag is polled one chunk late: chunk c is queued before the
+    // host waits for chunk c-1's flags, so the GPU never drains while the host
+    // reads them.  Iterations queued past convergence exit at once.
+    int slot = 0;
+    bool queued = false;
     while (!done && it < o.maxit) {
       const int chunk = std::min(check, o.maxit - it);
       for (int c = 0; c < chunk; ++c, ++it) {
@@ -445,10 +455,18 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
         const KEvents e2 = prof_slot(h, QP_PROF_CGPUPDATE, true);
         HIPCHK(launch_cg_pupdate(a, h->st, &e2));
       }
-      HIPCHK(hipMemcpyAsync(h->hfl, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
-      HIPCHK(hipStreamSynchronize(h->st));
-      done = h->hfl[F_DONE] != 0;
+      int* snap = h->hpoll + slot * F_COUNT;
+      HIPCHK(hipMemcpyAsync(snap, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipEventRecord(h->poll_ev[slot], h->st));
+      if (queued) {
+        HIPCHK(hipEventSynchronize(h->poll_ev[slot ^ 1]));
+        done = h->hpoll[(slot ^ 1) * F_COUNT + F_DONE] != 0;
+      }
+      queued = true;
+      slot ^= 1;
     }
+    CHK(read_back(h));   // flags after everything queued
+    done = h->hfl[F_DONE] != 0;
     if (!lo || h->hfl[F_STATUS] != 1) break;
     // Reduced-precision operator: the stop test saw the recurrence residual;
     // accept only if the float64 residual passes too, else restart from it.
@@ -1003,10 +1021,12 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   {
     hipError_t e1 = hipHostMalloc((void**)&h->hsc, sizeof(double) * S_COUNT, hipHostMallocDefault);
     hipError_t e2 = hipHostMalloc((void**)&h->hfl, sizeof(int) * F_COUNT, hipHostMallocDefault);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
+    hipError_t e3 = hipHostMalloc((void**)&h->hpoll, 2 * sizeof(int) * F_COUNT, hipHostMallocDefault);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
       h->err = "hipHostMalloc failed";
       return QP_ERR_ALLOC;
     }
+    for (hipEvent_t& e : h->poll_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
 
   CHK(upload(h, &h->diagH0, diagH.data(), n));
