@@ -394,6 +394,7 @@ static CgArgs cg_args(qp_handle h, const double* rhs, double* sol, const pcg_opt
   a.x = sol; a.r = h->cg_r; a.z = h->cg_z; a.p = h->cg_p; a.q = h->cg_q;
   a.rhs = rhs; a.jdiag = h->jdiag; a.part = h->part; a.fl = h->fl; a.sc = h->sc;
   a.g_vec = h->g_vec; a.g_r = h->nRP > 0 ? h->g_rmv : 0; a.g_x = h->g_xmv; a.has_ts = h->has_ts;
+  a.me = h->me;
   a.tol = o.tol; a.maxit = o.maxit;
   return a;
 }

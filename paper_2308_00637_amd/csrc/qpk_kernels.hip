@@ -734,35 +734,35 @@ __global__ __launch_bounds__(kBlock) void k_ts_reduce(TsArgs a) {
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_ts_finish(TsFinishArgs a) {
+  // Block l sums column l of the reduction's per-block partials (a.grid rows
+  // of k + me): thread t takes rows t, t + kBlock, ..., then the block tree.
   if (a.done && *a.done) return;
   const int KW = a.k + a.me;
-  for (int l = threadIdx.x; l < KW; l += kBlock) {
-    double s = 0.0;
-    for (int b = 0; b < a.grid; ++b) s += a.part[static_cast<int64_t>(b) * KW + l];
-    if (l < a.k) a.g[l] = a.wd[l] * s;
-    else a.te[l - a.k] = s;
+  const int l = blockIdx.x;
+  double s = 0.0;
+#pragma unroll 8
+  for (int b = threadIdx.x; b < a.grid; b += kBlock) s += a.part[static_cast<int64_t>(b) * KW + l];
+  s = block_sum(s);
+  if (threadIdx.x != 0) return;
+  if (l < a.k) {
+    a.g[l] = a.wd[l] * s;
+    return;
   }
-  __syncthreads();
-  double acc = 0.0;
+  const int e = l - a.k;
+  a.te[e] = s;
+  // equality row e: its term of the product (TS_MATVEC) or of the residual
+  // (TS_RESID); partout[e] is summed over e by the consumers
   if constexpr (MODE == TS_MATVEC) {
-    for (int e = threadIdx.x; e < a.me; e += kBlock) {
-      const double te = a.te[e], ve = a.vl[e];
-      a.we[e] = 2.0 * te / a.mu + ve;
-      const double ye = te + a.mu * ve;
-      a.yl[e] = ye;
-      acc += ve * ye;
-    }
+    const double ve = a.vl[e];
+    a.we[e] = 2.0 * s / a.mu + ve;
+    const double ye = s + a.mu * ve;
+    a.yl[e] = ye;
+    a.partout[e] = ve * ye;
   } else if constexpr (MODE == TS_RESID) {
-    for (int e = threadIdx.x; e < a.me; e += kBlock) {
-      const double re = a.te[e] - a.b[e] + a.mu * a.lam[e];
-      a.res[a.n + e] = re;
-      a.we[e] = -a.lam[e];
-      acc += re * re;
-    }
-  }
-  if constexpr (MODE == TS_MATVEC || MODE == TS_RESID) {
-    acc = block_sum(acc);
-    if (threadIdx.x == 0) a.partout[0] = acc;
+    const double re = s - a.b[e] + a.mu * a.lam[e];
+    a.res[a.n + e] = re;
+    a.we[e] = -a.lam[e];
+    a.partout[e] = re * re;
   }
 }
 
@@ -854,7 +854,8 @@ __global__ __launch_bounds__(kBlock) void k_finish_norms(VecArgs a, int g_r, int
   const double pr = sum_bcast(P + P_NR_PRIMAL * kGridMax, g_r) + sum_bcast(P + P_NX_PRIMAL * kGridMax, g_x);
   const double du = sum_bcast(P + P_NX_DUAL * kGridMax, g_x);
   const double co = sum_bcast(P + P_NR_COMPL * kGridMax, g_r) + sum_bcast(P + P_NX_COMPL * kGridMax, g_x);
-  const double re = P[P_NTS_RE * kGridMax];
+  double re = 0.0;
+  for (int e = 0; e < a.me; ++e) re += P[P_NTS_RE * kGridMax + e];
   if (threadIdx.x == 0) {
     a.sc[S_NORM] = sqrt(pr + du + co + re);
     a.sc[S_PRIMAL] = sqrt(pr);
@@ -1035,7 +1036,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
   sum3_bcast(P + P_DOT_R * kGridMax, a.g_r, P + P_DOT_X * kGridMax, a.g_x,
              P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec, pqr, pqx, rz);
   double pq = pqr + pqx;
-  if (a.has_ts) pq += P[P_DOT_TS * kGridMax];
+  if (a.has_ts)
+    for (int e = 0; e < a.me; ++e) pq += P[P_DOT_TS * kGridMax + e];
   if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.fl[F_STATUS] = (isfinite(pq) && isfinite(rz)) ? QP_ERR_NOT_SPD_CODE : QP_ERR_NUMERIC_CODE;
@@ -1385,9 +1387,11 @@ hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st, c
 }
 
 hipError_t launch_ts_finish(int mode, const TsFinishArgs& a, hipStream_t st) {
-  if (mode == TS_MATVEC) k_ts_finish<TS_MATVEC><<<1, kBlock, 0, st>>>(a);
-  else if (mode == TS_RESID) k_ts_finish<TS_RESID><<<1, kBlock, 0, st>>>(a);
-  else k_ts_finish<TS_GONLY><<<1, kBlock, 0, st>>>(a);
+  const int KW = a.k + a.me;
+  if (KW == 0) return hipSuccess;
+  if (mode == TS_MATVEC) k_ts_finish<TS_MATVEC><<<KW, kBlock, 0, st>>>(a);
+  else if (mode == TS_RESID) k_ts_finish<TS_RESID><<<KW, kBlock, 0, st>>>(a);
+  else k_ts_finish<TS_GONLY><<<KW, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
