@@ -1,0 +1,103 @@
+"""The blocked operator layouts and their kernel variants, on a radiation-
+therapy-shaped QP wide enough that both sides of K v need several LDS chunks
+(24,000 beamlets > 20,224 columns per row-side chunk; 42,000 voxel and
+max-dose rows > 10,112 columns per column-side chunk), so every PCG product
+runs the per-chunk partial kernels and both epilogues.  Against the oracle's
+matrix-free functions, and against each other: the staging variants and the
+two row directions change no arithmetic, so their products agree bitwise."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import from_masked, kkt_from_masked, kkt_to_masked, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def wide():
+    spec = W.rt_qp(5, 40_000, 24_000, 0.002, 2_000, name="rt_wide_40000x24000")
+    return spec, O.from_spec(spec)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def make_qp(spec, env):
+    from paper_2308_00637_amd.qpk import QP
+    keys = ("QPK_KV_R", "QPK_KV_X", "QPK_ALTERNATE")
+    old = {k: os.environ.get(k) for k in keys}
+    try:
+        for k in keys:
+            os.environ.pop(k, None)
+        os.environ.update({k: str(v) for k, v in env.items()})
+        return QP(spec)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def test_wide_layout_is_multi_chunk_on_both_sides(wide):
+    spec, _ = wide
+    lay = make_qp(spec, {}).operator_layout()
+    print(lay, flush=True)
+    assert lay["row"]["chunks"] == 2 and lay["col"]["chunks"] >= 4
+
+
+def test_wide_matvec_and_pcg_against_oracle(wide):
+    spec, prob = wide
+    qp = make_qp(spec, {})
+    qp.init_state(1.0)
+    st = O.initial_point(prob)
+    rhs, dg = qp.newton_rhs()
+    ref_rhs, _ = O.newton_rhs_doubly(prob, st, 1.0)
+    assert rel(kkt_from_masked(prob, rhs.cpu().numpy()), ref_rhs) <= 1e-12
+    assert rel(kkt_from_masked(prob, dg.cpu().numpy()), O.jacobi_diagonal(prob, st, 1.0)) <= 1e-12
+    v = np.random.default_rng(1).standard_normal(ref_rhs.size)
+    y = qp.kkt_matvec(dev(kkt_to_masked(prob, v)))
+    assert rel(kkt_from_masked(prob, y.cpu().numpy()), O.kkt_matvec(prob, st, 1.0, v)) <= 1e-12
+    sol, info = qp.kkt_pcg_solve(rhs)
+    assert info.converged == 1
+    solc = kkt_from_masked(prob, sol.cpu().numpy())
+    true_rel = np.linalg.norm(ref_rhs - O.kkt_matvec(prob, st, 1.0, solc)) / np.linalg.norm(ref_rhs)
+    print(f"pcg iters={info.iterations} true relres={true_rel:.3e}", flush=True)
+    assert true_rel <= 1.5e-7
+
+
+@pytest.mark.parametrize("env", [{"QPK_KV_R": 1}, {"QPK_KV_X": 0}, {"QPK_ALTERNATE": 0}])
+def test_variants_and_directions_agree_bitwise(wide, env):
+    spec, prob = wide
+    base = make_qp(spec, {})
+    other = make_qp(spec, env)
+    v = dev(kkt_to_masked(prob, np.random.default_rng(2).standard_normal(
+        prob.n + prob.me + len(O.index_sets(prob).L) + len(O.index_sets(prob).U))))
+    for qp in (base, other):
+        qp.init_state(1.0)
+        qp.newton_rhs()
+    # two products in a row: the default alternates the row direction between them
+    y0, y1 = base.kkt_matvec(v), base.kkt_matvec(v)
+    z0, z1 = other.kkt_matvec(v), other.kkt_matvec(v)
+    assert torch.equal(y0, y1)
+    assert torch.equal(y0, z0) and torch.equal(y0, z1)
+
+
+def test_wide_ipm_solve_kkt_by_oracle_function(wide):
+    spec, prob = wide
+    qp = make_qp(spec, {})
+    out = qp.solve()
+    info = out["info"]
+    print(f"ipm={info.iterations} cg={info.total_cg_iters} time={info.time_ms / 1e3:.2f}s "
+          f"rnorm={info.rnorm:.3e}", flush=True)
+    assert info.result == 0 and info.mu_final < 1e-6
+    gst = from_masked(prob, out["x"].cpu().numpy(), out["lam"].cpu().numpy(), out["s"].cpu().numpy())
+    kkt = O.stacked_norm(O.residuals(prob, gst, info.mu_final))
+    assert kkt <= 1e-6 and kkt == pytest.approx(info.rnorm, rel=1e-9)
+    assert info.objective == pytest.approx(O.objective(prob, gst.x), rel=1e-12)
