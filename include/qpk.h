@@ -302,8 +302,9 @@ qp_status qp_update_data(qp_handle h, const double* c, const double* lA, const d
  * category's time is kernel execution only, comparable to a profiler's kernel
  * trace.  A timed dispatch costs a few microseconds of queue time around it;
  * every > 1 keeps that out of all but a sample.  qp_profile_end synchronises
- * and returns, per category, the number of timed dispatches and their summed
- * duration in ms (HOST arrays of QP_PROF_COUNT entries), then frees the
+ * and returns, per category, the number of timed dispatches, their summed
+ * duration in ms, and the number of dispatches made while profiling, timed
+ * or not (HOST arrays of QP_PROF_COUNT entries; any may be NULL), then frees the
  * events.  Categories (one kernel each): */
 enum {
   QP_PROF_ROWPASS = 0,    /* row-side operator kernel of K v (rows of P and A) */
@@ -315,7 +316,7 @@ enum {
   QP_PROF_COUNT = 6
 };
 qp_status qp_profile_begin(qp_handle h, int32_t max_launches, int32_t every);
-qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms);
+qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms, int64_t* dispatches);
 
 /* Bytes of the stored operators (HOST out): row-side CSR, column-side CSR,
  * dense low-rank factor, each in the precision the PCG matvec reads, plus

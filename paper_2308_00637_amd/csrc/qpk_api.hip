@@ -235,8 +235,8 @@ static TsFinishArgs tsf_args(qp_handle h) {
 // is on and the category still has free slots).
 static KEvents prof_slot(qp_handle h, int c, bool active) {
   KEvents e;
-  if (!active || !h->prof.on || h->prof.used[c] >= h->prof.cap) return e;
-  if (h->prof.seen[c]++ % h->prof.every != 0) return e;
+  if (!active || !h->prof.on) return e;
+  if (h->prof.seen[c]++ % h->prof.every != 0 || h->prof.used[c] >= h->prof.cap) return e;
   const int slot = h->prof.used[c]++;
   e.start = h->prof.ev[c][2 * slot];
   e.stop = h->prof.ev[c][2 * slot + 1];
@@ -1375,7 +1375,7 @@ qp_status qp_profile_begin(qp_handle h, int32_t max_launches, int32_t every) {
   return QP_OK;
 }
 
-qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms) {
+qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms, int64_t* dispatches) {
   if (!h || !h->prof.on) return QP_ERR_STATE;
   HIPCHK(hipStreamSynchronize(h->st));
   for (int c = 0; c < QP_PROF_COUNT; ++c) {
@@ -1387,9 +1387,11 @@ qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms) {
     }
     if (launches) launches[c] = h->prof.used[c];
     if (total_ms) total_ms[c] = tot;
+    if (dispatches) dispatches[c] = h->prof.seen[c];
     for (hipEvent_t e : h->prof.ev[c]) (void)hipEventDestroy(e);
     h->prof.ev[c].clear();
     h->prof.used[c] = 0;
+    h->prof.seen[c] = 0;
   }
   h->prof.on = false;
   h->prof.cap = 0;

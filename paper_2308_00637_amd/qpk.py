@@ -117,7 +117,7 @@ def _load():
         "ipm_solve": (C.c_int, [vp, C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo)]),
         "qp_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, C.POINTER(PcgOptions), C.POINTER(PcgInfo)]),
         "qp_profile_begin": (C.c_int, [vp, C.c_int32, C.c_int32]),
-        "qp_profile_end": (C.c_int, [vp, _i64p, _dp]),
+        "qp_profile_end": (C.c_int, [vp, _i64p, _dp, _i64p]),
         "qp_operator_bytes": (C.c_int, [vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
         "qp_operator_layout": (C.c_int, [vp, _i32p, _i32p, _i32p]),
         "qp_update_data": (C.c_int, [vp, vp, vp, vp, vp, vp]),
@@ -366,10 +366,12 @@ class QP:
         self._check(LIB.qp_profile_begin(self.h, int(max_launches), int(every)))
 
     def profile_end(self):
+        """Per category: (timed dispatches, their summed ms, all dispatches)."""
         cnt = (C.c_int64 * len(PROF_CATEGORIES))()
         ms = (C.c_double * len(PROF_CATEGORIES))()
-        self._check(LIB.qp_profile_end(self.h, cnt, ms))
-        return {k: (int(cnt[i]), float(ms[i])) for i, k in enumerate(PROF_CATEGORIES)}
+        seen = (C.c_int64 * len(PROF_CATEGORIES))()
+        self._check(LIB.qp_profile_end(self.h, cnt, ms, seen))
+        return {k: (int(cnt[i]), float(ms[i]), int(seen[i])) for i, k in enumerate(PROF_CATEGORIES)}
 
     def operator_bytes(self):
         v = [C.c_int64() for _ in range(5)]
