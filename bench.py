@@ -354,7 +354,7 @@ def main():
     dom = max(kern, key=lambda c: kern[c]["avg_us"])
     d = kern[dom]
     per_iter_us = sum(v["avg_us"] for v in kern.values())
-    traffic = stored_traffic(spec.name, args.precision, dom)
+    traffic = stored_traffic(args.workload, args.precision, dom)
     result = {
         "metric": METRIC,
         "value": total_cg / solve_s,
