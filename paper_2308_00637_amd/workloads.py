@@ -211,6 +211,54 @@ def batch_qps(seed: int = 3, count: int = 256, nmin: int = 500, nmax: int = 8000
             for i, (n, m, r) in enumerate(batch_sizes(seed, count, nmin, nmax))]
 
 
+def _csr_from_lengths(rng: np.random.Generator, lengths, ncols: int, col_hi: int) -> sp.csr_matrix:
+    """CSR whose row i has lengths[i] distinct uniform columns in [0, col_hi),
+    values exp(N(-3, 1))."""
+    indptr = np.zeros(len(lengths) + 1, dtype=np.int64)
+    cols = []
+    for i, k in enumerate(lengths):
+        c = np.sort(rng.choice(col_hi, size=int(k), replace=False)) if k else np.zeros(0, np.int64)
+        cols.append(c)
+        indptr[i + 1] = indptr[i] + len(c)
+    cols = np.concatenate(cols).astype(np.int32) if cols else np.zeros(0, np.int32)
+    vals = np.exp(rng.normal(-3.0, 1.0, size=cols.size))
+    return sp.csr_matrix((vals, cols, indptr.astype(np.int32)), shape=(len(lengths), ncols))
+
+
+def ragged_qp(seed: int, n: int = 901, p_rows: int = 1503, m: int = 407) -> QPSpec:
+    """Radiation-therapy-shaped QP with ragged structure: rows of P and A from
+    empty to several hundred entries (longer than one batch of the blocked
+    passes), the last tenth of the variables in no row of A, variables free,
+    lower-, upper- and two-side bounded, rows two-sided, one-sided and free.
+    Feasible around x0 ~ U(0.2, 0.8).
+
+    Draw order: P lengths, P, A lengths, A, w, d, x0, variable bound kinds,
+    row bound kinds, row margins, variable margins.
+    """
+    rng = np.random.default_rng(seed)
+    pl = np.where(rng.random(p_rows) < 0.03, rng.integers(300, 600, p_rows), rng.poisson(25, p_rows))
+    pl[rng.random(p_rows) < 0.05] = 0
+    P = _csr_from_lengths(rng, np.minimum(pl, n), n, n)
+    al = np.where(rng.random(m) < 0.1, rng.integers(150, 400, m), rng.poisson(6, m))
+    al[rng.random(m) < 0.1] = 0
+    col_hi = int(0.9 * n)
+    A = _csr_from_lengths(rng, np.minimum(al, col_hi), n, col_hi)
+    w = np.where(rng.random(p_rows) < 0.1, 10.0, 1.0)
+    d = rng.uniform(0.0, 1.0, p_rows)
+    x0 = rng.uniform(0.2, 0.8, n)
+    vk = rng.integers(0, 4, n)                  # 0 free, 1 lower, 2 upper, 3 both
+    rk = rng.integers(0, 4, m)                  # 0 both, 1 lower, 2 upper, 3 free row
+    ax = A @ x0
+    mlo, mhi = rng.uniform(0.05, 0.5, m), rng.uniform(0.05, 0.5, m)
+    lA = np.where((rk == 0) | (rk == 1), ax - mlo, -np.inf)
+    uA = np.where((rk == 0) | (rk == 2), ax + mhi, np.inf)
+    vlo, vhi = rng.uniform(0.1, 0.2, n), rng.uniform(0.1, 0.2, n)
+    lx = np.where((vk == 1) | (vk == 3), x0 - vlo, -np.inf)
+    ux = np.where((vk == 2) | (vk == 3), x0 + vhi, np.inf)
+    return QPSpec(n=n, c=np.zeros(n), h_kind="ptwp", P=P, w=w, d=d, A=A, lA=lA, uA=uA,
+                  lx=lx, ux=ux, name=f"ragged_{n}x{p_rows}x{m}")
+
+
 def random_bounded_qp(seed: int, n: int, m: int, me: int, mg: int,
                       a_sparse: bool = False, two_sided: bool = True,
                       h_kind: str = "dense") -> QPSpec:

@@ -1,8 +1,9 @@
 """The blocked operator layouts and their kernel variants, on a radiation-
 therapy-shaped QP wide enough that both sides of K v need several LDS chunks
-(24,000 beamlets > 20,224 columns per row-side chunk; 42,000 voxel and
-max-dose rows > 10,112 columns per column-side chunk), so every PCG product
-runs the per-chunk partial kernels and both epilogues.  Against the oracle's
+(24,001 beamlets > 20,224 columns per row-side chunk; 42,001 voxel and
+max-dose rows > 10,112 columns per column-side chunk; both last chunks have
+odd width), so every PCG product runs the per-chunk partial kernels and both
+epilogues.  Against the oracle's
 matrix-free functions, and against each other: the staging variants and the
 two row directions change no arithmetic, so their products agree bitwise."""
 import os
@@ -20,7 +21,8 @@ torch = pytest.importorskip("torch")
 
 @pytest.fixture(scope="module")
 def wide():
-    spec = W.rt_qp(5, 40_000, 24_000, 0.002, 2_000, name="rt_wide_40000x24000")
+    # odd sizes: the last chunk of either side has an odd width
+    spec = W.rt_qp(5, 40_001, 24_001, 0.002, 2_000, name="rt_wide_40001x24001")
     return spec, O.from_spec(spec)
 
 

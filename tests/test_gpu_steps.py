@@ -2,6 +2,7 @@
 the C ABI (steps a1-a8 at arbitrary interior states, then Algorithm 1)."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle as O
 from paper_2308_00637_amd import workloads as W
@@ -24,6 +25,14 @@ def _cases():
         "no_rows_bounds_only": lambda: W.QPSpec(n=70, c=np.linspace(-3, 3, 70), h_kind="dense",
                                                 H=np.diag(np.linspace(0.5, 2, 70)),
                                                 lx=-np.ones(70), ux=np.ones(70)),
+        # empty and several-hundred-entry rows, variables in no row, free rows
+        "ragged_ptwp": lambda: W.ragged_qp(9),
+        "single_variable": lambda: W.QPSpec(
+            n=1, c=np.array([-1.0]), h_kind="ptwp",
+            P=sp.csr_matrix(np.array([[1.0], [0.5], [2.0]])), w=np.ones(3), d=np.array([0.3, 0.1, 0.9]),
+            A=sp.csr_matrix(np.array([[2.0]])), lA=np.array([-np.inf]), uA=np.array([1.0]),
+            lx=np.zeros(1), ux=np.full(1, np.inf)),
+        "max_equalities": lambda: W.random_bounded_qp(3, 150, 40, 64, 20),
     }
 
 
