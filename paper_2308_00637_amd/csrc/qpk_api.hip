@@ -631,8 +631,8 @@ const char* qp_last_error(qp_handle h) { return h ? h->err.c_str() : g_create_er
 // fit one wave of blocks (one block per CU, 256 CUs).
 static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
                                const std::vector<int32_t>& col, const std::vector<double>& val,
-                               int ncols, int cw_default, int kv_default, const char* env,
-                               const char* env_lpr, const char* env_kv) {
+                               int ncols, int cw_default, int kv_default, bool row_side,
+                               const char* env, const char* env_lpr, const char* env_kv) {
   const int64_t nrows = (int64_t)rp.size() - 1;
   // Chunk width (columns staged in LDS per block); `env` overrides it.
   int cw = cw_default;
@@ -708,7 +708,13 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   ck.nnz = nnz;
   ck.stored = stored;
   const double avg = nrows > 0 ? (double)nnz / ((double)nrows * nchunk) : 1.0;
+  // lanes per row: about four entries per lane; a single-chunk row side runs
+  // eight pairs per lane at up to 8 lanes (see k_chunked), so ~16 entries
   ck.lpr = pow2_clamp(avg / 4.0, 4, 64);
+  if (row_side && nchunk == 1) {
+    ck.lpr = 4;
+    while (ck.lpr < 64 && ck.lpr * (ck.lpr <= 8 ? 16 : 8) < avg) ck.lpr *= 2;
+  }
   if (const char* e = std::getenv(env_lpr)) ck.lpr = pow2_clamp(std::atof(e), 4, 64);
   ck.kv = kv_default;
   if (const char* e = std::getenv(env_kv)) ck.kv = std::atoi(e) & 1;
@@ -927,10 +933,10 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   // half-LDS chunks staged straight into LDS, two blocks per CU (both
   // measured fastest on the radiation-therapy workload).
   if (h->nRP > 0)
-    CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, "QPK_CHUNK_COLS_R",
+    CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, true, "QPK_CHUNK_COLS_R",
                       "QPK_LPR_R", "QPK_KV_R"));
   if (want_ck_x)
-    CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1,
+    CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1, false,
                       "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
   if (const char* e = std::getenv("QPK_ALTERNATE")) h->alternate = std::atoi(e) != 0;
   h->g_epi_r = grid_cap(std::max<int64_t>(h->nRP, 1), kBlock, kGridMax);
