@@ -708,16 +708,19 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   ck.nnz = nnz;
   ck.stored = stored;
   const double avg = nrows > 0 ? (double)nnz / ((double)nrows * nchunk) : 1.0;
-  // lanes per row: about four entries per lane; a single-chunk row side runs
-  // eight pairs per lane at up to 8 lanes (see k_chunked), so ~16 entries
+  ck.kv = kv_default;
+  if (const char* e = std::getenv(env_kv)) ck.kv = std::atoi(e) & 1;
+  // Lanes per row.  A float64 pass staged through registers (kv 0) takes eight
+  // entry pairs per lane at up to 8 lanes per row, the others four (see
+  // k_chunked): size the group so one batch covers a typical row, the
+  // single-chunk row side (the hot one, float64) generously, else about four
+  // entries per lane.
   ck.lpr = pow2_clamp(avg / 4.0, 4, 64);
-  if (row_side && nchunk == 1) {
+  if (row_side && nchunk == 1 && h->vk == VK_F64 && ck.kv == 0) {
     ck.lpr = 4;
     while (ck.lpr < 64 && ck.lpr * (ck.lpr <= 8 ? 16 : 8) < avg) ck.lpr *= 2;
   }
   if (const char* e = std::getenv(env_lpr)) ck.lpr = pow2_clamp(std::atof(e), 4, 64);
-  ck.kv = kv_default;
-  if (const char* e = std::getenv(env_kv)) ck.kv = std::atoi(e) & 1;
   CHK(upload(h, &ck.work, work.data(), (int64_t)work.size()));
   CHK(upload(h, &ck.rowptr, crp.data(), (int64_t)crp.size()));
   CHK(upload(h, &ck.col, ccol.data(), stored));

@@ -504,9 +504,10 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
   const int lane = threadIdx.x & (LPR - 1);
   const int gid = threadIdx.x / LPR;
   constexpr int NG = kChunkBlock / LPR;
-  // entry pairs per lane per batch: the single-chunk row pass (one block per
-  // CU, so up to 128 VGPRs) takes eight, twice the entries in flight per wave
-  constexpr int PP = (EPI == CE_ROW && LPR <= 8) ? 8 : 4;
+  // entry pairs per lane per batch: a pass staged through registers runs one
+  // block per CU (a full-LDS chunk), so up to 128 VGPRs, and takes eight at
+  // up to 8 lanes per row, twice the entries in flight per wave
+  constexpr int PP = (!DMA && LPR <= 8) ? 8 : 4;
   constexpr int SPAN = 2 * LPR * PP;         // entries per group per batch
   using LT = decltype(ldv(val, 0));          // loaded value type
 
