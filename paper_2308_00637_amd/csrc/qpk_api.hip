@@ -634,8 +634,12 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
                                int ncols, int cw_default, int kv_default, bool row_side,
                                const char* env, const char* env_lpr, const char* env_kv) {
   const int64_t nrows = (int64_t)rp.size() - 1;
-  // Chunk width (columns staged in LDS per block); `env` overrides it.
+  // Chunk width (columns staged in LDS per block); `env` overrides it.  A
+  // work item holds at least one (chunk, row) segment, so few long rows (a
+  // handful of dense rows over many columns) get narrower chunks until there
+  // are segments for two blocks per CU.
   int cw = cw_default;
+  while (cw > 1024 && nrows * ((ncols + cw - 1) / cw) < 512) cw = std::max(1024, cw / 2) & ~1;
   if (const char* e = std::getenv(env)) {
     const int v = std::atoi(e);
     if (v >= 1024 && v <= kChunkCols) cw = v & ~1;
@@ -708,7 +712,8 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   ck.nnz = nnz;
   ck.stored = stored;
   const double avg = nrows > 0 ? (double)nnz / ((double)nrows * nchunk) : 1.0;
-  ck.kv = kv_default;
+  // multi-chunk passes stage straight into LDS: 64 VGPRs, two blocks per CU
+  ck.kv = nchunk > 1 ? 1 : kv_default;
   if (const char* e = std::getenv(env_kv)) ck.kv = std::atoi(e) & 1;
   // Lanes per row.  A float64 pass staged through registers (kv 0) takes eight
   // entry pairs per lane at up to 8 lanes per row, the others four (see

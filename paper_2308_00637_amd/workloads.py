@@ -259,6 +259,32 @@ def ragged_qp(seed: int, n: int = 901, p_rows: int = 1503, m: int = 407) -> QPSp
                   lx=lx, ux=ux, name=f"ragged_{n}x{p_rows}x{m}")
 
 
+def qn_rt(seed: int = 6, n: int = 90_657, k: int = 20, m: int = 15) -> QPSpec:
+    """Quasi-Newton radiation-therapy subproblem shape (the proton liver case
+    of Table 1: 90,657 variables, 15 general rows, a bound on every variable):
+    H = diag(h0) + U diag(w) U^T with mixed-sign w, as a limited-memory BFGS
+    Hessian has, kept positive definite: h0 >= 0.5, the columns of U have norm
+    about 1, and the negative weights sum to at most 0.4 in magnitude.
+    Rows lA <= Ax <= uA two-sided around A x0, x >= 0.
+
+    Draw order: h0, U, positive weights, negative weights, c, A, x0, row margins.
+    """
+    rng = np.random.default_rng(seed)
+    h0 = rng.uniform(0.5, 1.5, n)
+    U = rng.standard_normal((n, k)) / np.sqrt(n)
+    kp = k - k // 2
+    wpos = rng.uniform(0.5, 2.0, kp)
+    wneg = -rng.uniform(0.2, 0.4, k - kp) / max(1, k - kp)
+    c = rng.standard_normal(n)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    x0 = rng.uniform(0.0, 1.0, n)
+    ax = A @ x0
+    mlo, mhi = rng.uniform(0.05, 0.5, m), rng.uniform(0.05, 0.5, m)
+    return QPSpec(n=n, c=c, h_kind="lowrank", h0=h0, U=np.ascontiguousarray(U),
+                  wd=np.concatenate([wpos, wneg]), A=A, lA=ax - mlo, uA=ax + mhi,
+                  lx=np.zeros(n), ux=np.full(n, np.inf), name=f"qn_rt_{n}x{k}_m{m}")
+
+
 def random_bounded_qp(seed: int, n: int, m: int, me: int, mg: int,
                       a_sparse: bool = False, two_sided: bool = True,
                       h_kind: str = "dense") -> QPSpec:

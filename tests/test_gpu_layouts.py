@@ -74,7 +74,7 @@ def test_wide_matvec_and_pcg_against_oracle(wide):
     assert true_rel <= 1.5e-7
 
 
-@pytest.mark.parametrize("env", [{"QPK_KV_R": 1}, {"QPK_KV_X": 0}, {"QPK_ALTERNATE": 0}])
+@pytest.mark.parametrize("env", [{"QPK_KV_R": 0}, {"QPK_KV_X": 0}, {"QPK_ALTERNATE": 0}])
 def test_variants_and_directions_agree_bitwise(wide, env):
     spec, prob = wide
     base = make_qp(spec, {})

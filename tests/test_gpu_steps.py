@@ -33,6 +33,8 @@ def _cases():
             A=sp.csr_matrix(np.array([[2.0]])), lA=np.array([-np.inf]), uA=np.array([1.0]),
             lx=np.zeros(1), ux=np.full(1, np.inf)),
         "max_equalities": lambda: W.random_bounded_qp(3, 150, 40, 64, 20),
+        # H = diag(h0) + U diag(w) U^T with mixed-sign w (limited-memory BFGS form)
+        "quasi_newton_mixed_w": lambda: W.qn_rt(6, 300, 12, 15),
     }
 
 
