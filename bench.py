@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rt_full",
-                    choices=["rt_full", "rt_small", "svm_full", "qn_rt", "tiny_dense"])
+                    choices=["rt_full", "rt_small", "svm_full", "svm_rbf", "qn_rt", "tiny_dense"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16", "fp32x64", "bf16x64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
@@ -66,7 +66,7 @@ def parse():
 def workload(name):
     from paper_2308_00637_amd import workloads as W
     return {"rt_full": W.rt_full, "rt_small": W.rt_small, "svm_full": W.svm_full,
-            "qn_rt": W.qn_rt, "tiny_dense": W.tiny_dense}[name]()
+            "svm_rbf": W.svm_rbf, "qn_rt": W.qn_rt, "tiny_dense": W.tiny_dense}[name]()
 
 
 def kernel_bytes(spec, ob, lay, cat, prec_bytes):

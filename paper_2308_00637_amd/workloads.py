@@ -187,6 +187,27 @@ def svm_qp(seed: int, n_samples: int, n_feat: int, box: float = 1.0,
                   extra={"y": y})
 
 
+def svm_rbf(seed: int = 7, n_samples: int = 1605, n_feat: int = 123, box: float = 1.0,
+            name: str = "") -> QPSpec:
+    """SVM dual with a precomputed dense RBF-kernel Hessian at the a1a shape of
+    Table 1 (1,605 samples, one equality row, 3,210 bounds).  Synthetic
+    two-Gaussian data stand in for a1a: y = +-1 with probability 1/2, features
+    X_i ~ N(0.3 y_i 1, I); H_ij = y_i y_j exp(-g |X_i - X_j|^2) with
+    g = 1 / n_feat.  Draw order: y, X.
+    """
+    rng = np.random.default_rng(seed)
+    y = np.where(rng.random(n_samples) < 0.5, 1.0, -1.0)
+    X = rng.standard_normal((n_samples, n_feat)) + 0.3 * y[:, None]
+    sq = (X * X).sum(1)
+    d2 = np.maximum(sq[:, None] + sq[None, :] - 2.0 * (X @ X.T), 0.0)
+    H = np.exp(-d2 / n_feat) * np.outer(y, y)
+    H = 0.5 * (H + H.T)
+    return QPSpec(n=n_samples, c=-np.ones(n_samples), h_kind="dense", H=H,
+                  C=y[None, :].copy(), b=np.zeros(1),
+                  lx=np.zeros(n_samples), ux=np.full(n_samples, box),
+                  name=name or f"svm_rbf_{n_samples}x{n_feat}", extra={"y": y, "X": X})
+
+
 def svm_full(seed: int = 2) -> QPSpec:
     return svm_qp(seed, 500_000, 128, name="svm_500000x128")
 

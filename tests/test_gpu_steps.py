@@ -35,6 +35,8 @@ def _cases():
         "max_equalities": lambda: W.random_bounded_qp(3, 150, 40, 64, 20),
         # H = diag(h0) + U diag(w) U^T with mixed-sign w (limited-memory BFGS form)
         "quasi_newton_mixed_w": lambda: W.qn_rt(6, 300, 12, 15),
+        # SVM dual with a dense RBF-kernel Hessian, one equality row, a box
+        "svm_rbf_dense": lambda: W.svm_rbf(7, 300),
     }
 
 

@@ -52,3 +52,25 @@ def test_svm_full_against_stored_oracle_result():
     spec = W.svm_full()
     out = QP(spec).solve()
     check(spec, out, g["objective"], np.array(g["w_svm"]))
+
+
+def test_svm_rbf_at_a1a_shape_against_dense_oracle():
+    """Dense precomputed RBF-kernel Hessian, 1,605 samples (the a1a shape of
+    Table 1), against the dense oracle's full solve."""
+    from paper_2308_00637_amd.qpk import QP
+    spec = W.svm_rbf(7)
+    prob = O.from_spec(spec)
+    ref = O.solve(prob)
+    out = QP(spec).solve()
+    info = out["info"]
+    alpha = out["x"].cpu().numpy()
+    st = from_masked(prob, alpha, out["lam"].cpu().numpy(), out["s"].cpu().numpy())
+    kkt = O.stacked_norm(O.residuals(prob, st, info.mu_final))
+    print(f"svm_rbf: ipm={info.iterations} (oracle {ref.iterations}) cg={info.total_cg_iters} "
+          f"time={info.time_ms / 1e3:.2f}s obj={info.objective:.12g} ref={ref.objective:.12g} "
+          f"kkt={kkt:.2e}", flush=True)
+    assert info.result == 0 and ref.status == "converged"
+    assert abs(info.objective - ref.objective) <= 1e-6 * max(1.0, abs(ref.objective))
+    assert kkt <= 1e-6
+    assert rel(alpha, ref.state.x) <= 1e-3
+    assert alpha.min() >= -1e-9 and alpha.max() <= 1 + 1e-9
