@@ -62,6 +62,7 @@ struct qp_handle_s {
   struct Chunked {
     bool on = false;
     int nrows = 0, ncols = 0, nchunk = 0, nwork = 0, lpr = 16, chunk_cols = kChunkCols, kv = kKvDefault;
+    int xcd_map = 1;
     int32_t* work = nullptr;
     int32_t* rowptr = nullptr;
     uint16_t* col = nullptr;
@@ -294,6 +295,7 @@ static qp_status prepare(qp_handle h) {
 static ChunkArgs chunk_args(const qp_handle_s::Chunked& k, bool lo, const double* src, bool reverse) {
   ChunkArgs c{};
   c.reverse = reverse ? 1 : 0;
+  c.xcd_map = k.xcd_map;
   c.nrows = k.nrows; c.ncols = k.ncols; c.nchunk = k.nchunk; c.chunk_cols = k.chunk_cols;
   c.work = k.work; c.rowptr = k.rowptr; c.col = k.col;
   c.val = lo ? k.val_lo : (const void*)k.val;
@@ -726,6 +728,7 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
     while (ck.lpr < 64 && ck.lpr * (ck.lpr <= 8 ? 16 : 8) < avg) ck.lpr *= 2;
   }
   if (const char* e = std::getenv(env_lpr)) ck.lpr = pow2_clamp(std::atof(e), 4, 64);
+  if (const char* e = std::getenv("QPK_XCD_MAP")) ck.xcd_map = std::atoi(e) != 0;
   CHK(upload(h, &ck.work, work.data(), (int64_t)work.size()));
   CHK(upload(h, &ck.rowptr, crp.data(), (int64_t)crp.size()));
   CHK(upload(h, &ck.col, ccol.data(), stored));

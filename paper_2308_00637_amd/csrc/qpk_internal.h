@@ -176,6 +176,7 @@ struct ChunkArgs {
   int32_t nstored;           // stored entries (with the even-length padding)
   int32_t kv;                // chunk staging: 0 through registers, 1 direct to LDS
   int32_t reverse;           // visit each work item's rows last to first
+  int32_t xcd_map;           // runs of consecutive work items per XCD (see k_chunked)
 };
 constexpr int kKvDefault = 1;
 enum ChunkEpi : int { CE_PARTIAL = 0, CE_ROW = 1, CE_COL = 2 };

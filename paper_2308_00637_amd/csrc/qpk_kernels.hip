@@ -445,6 +445,13 @@ __device__ double block_sum_nt(double v) {
   return r;
 }
 
+// Bijection of [0, g): the blocks i with i mod 8 == x map to the x-th
+// contiguous run of items.
+__device__ __forceinline__ int xcd_item(int i, int g) {
+  const int x = i & 7, slot = i >> 3, q = g >> 3, r = g & 7;
+  return x * q + min(x, r) + slot;
+}
+
 // Raw buffer resources: a load whose byte offset is at or past num_records
 // returns zero without touching memory, so loads past a segment's end need no
 // branch.  kOob is such an offset for every array here (all are < 2 GiB).
@@ -495,7 +502,12 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
     if (ca.bump && blockIdx.x == 0 && threadIdx.x == 0) *ca.bump += 1;
   }
   extern __shared__ __align__(16) double lds[];
-  const int c = b.work[3 * blockIdx.x], r0 = b.work[3 * blockIdx.x + 1], r1 = b.work[3 * blockIdx.x + 2];
+  // Work items are stored chunk by chunk.  Blocks go to the 8 XCDs round
+  // robin (block i on XCD i mod 8), so block i takes item xcd_item(i): the
+  // blocks of one XCD take a contiguous run of items, i.e. a few chunks, whose
+  // gathered vector its own L2 then fetches once.
+  const int wi = b.xcd_map ? xcd_item(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+  const int c = b.work[3 * wi], r0 = b.work[3 * wi + 1], r1 = b.work[3 * wi + 2];
   const int32_t* rp = b.rowptr + static_cast<int64_t>(c) * (b.nrows + 1);
   const T* val = static_cast<const T*>(b.val);
   const __amdgpu_buffer_rsrc_t rrp = rsrc(rp, 4u * static_cast<uint32_t>(b.nrows + 1));
