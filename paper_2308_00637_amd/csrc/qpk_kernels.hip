@@ -279,11 +279,15 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
     Acc acc = 0, acc2 = 0;
     if (val) {
       const int b0 = a.rowptr[j], b1 = a.seg1[j], b2 = a.seg2[j], b3 = a.rowptr[j + 1];
+      // unrolled so that each lane has several entries' loads in flight
+      // (same summation order)
       if (MODE != X_RHS && MODE != X_DIAGH && MODE != X_CEFF && a.use_hx) {
+#pragma unroll 8
         for (int q = b0 + lane; q < b1; q += LPR)
           acc += ldv(val, q) * static_cast<Acc>(a.src_hx[a.col[q]]);
       }
       if (a.use_pt) {
+#pragma unroll 4
         for (int q = b1 + lane; q < b2; q += LPR) {
           const int c = a.col[q];
           const Acc vv = ldv(val, q);
@@ -293,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
         }
       }
       if (a.use_at) {
+#pragma unroll 4
         for (int q = b2 + lane; q < b3; q += LPR) {
           const int c = a.col[q];
           const Acc vv = ldv(val, q);
