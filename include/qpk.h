@@ -125,6 +125,12 @@ typedef struct {
   int32_t rr_period;         /* reduced precision only: replace r by the float64 residual
                               * rhs - K x every rr_period iterations (search direction kept);
                               * default 0 = only when the stop test fires */
+  int32_t spectrum;          /* 1: estimate the extreme eigenvalues of the Jacobi-
+                              * preconditioned matrix diag(K)^-1 K from the CG coefficients
+                              * (the Lanczos tridiagonal matrix that CG builds implicitly),
+                              * reported in pcg_info; the condition number diagnostic of
+                              * Section 5.3.  Float64 solves without restarts only.
+                              * Default 0 */
 } pcg_options;
 
 typedef struct {
@@ -137,6 +143,9 @@ typedef struct {
                               * reduced-precision operator (iteration cap, NaN, or lost
                               * positive definiteness) and was redone in float64;
                               * iterations then counts both attempts */
+  double lambda_min;         /* spectrum = 1: smallest and largest Ritz value of the */
+  double lambda_max;         /* CG tridiagonal matrix (inside the spectrum of diag(K)^-1 K,
+                              * converging to its ends); 0 when not estimated */
 } pcg_info;
 
 /* Algorithm 1 settings.  gamma of eq. (10); mu is divided by mu_div when the
@@ -161,6 +170,8 @@ typedef struct {
   double* log_alpha_lam;
   int32_t* log_cg_iters;
   double* log_cg_relres;
+  double* log_kappa;         /* lambda_max / lambda_min of each Newton system (needs
+                              * pcg.spectrum = 1), or NULL */
 } ipm_options;
 
 typedef enum { QP_IPM_CONVERGED = 0, QP_IPM_MAX_ITER = 1 } qp_ipm_result;

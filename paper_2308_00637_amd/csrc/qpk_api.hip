@@ -77,6 +77,8 @@ struct qp_handle_s {
   bool alternate = true;                 // alternate the row direction of the blocked passes
   int64_t n_matvec = 0;                  // blocked K v products so far
   double* uw = nullptr;  // [u (p_rows) | wA (m)] for the PCG matvec
+  double* coef = nullptr;  // CG alpha/beta record (spectrum estimates), 2 * coef_cap
+  int coef_cap = 0;
   std::vector<void*> allocs;
   // optional event timing of PCG launches
   struct Prof {
@@ -408,6 +410,41 @@ static qp_status read_back(qp_handle h) {
   return QP_OK;
 }
 
+// Extreme eigenvalues of the symmetric tridiagonal matrix (diagonal d, off-
+// diagonal e, size k) by Sturm-sequence bisection.
+static void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e,
+                             double* lo_out, double* hi_out) {
+  const int k = (int)d.size();
+  double lo = INFINITY, hi = -INFINITY;
+  for (int j = 0; j < k; ++j) {
+    const double r = (j > 0 ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < k ? std::fabs(e[j]) : 0.0);
+    lo = std::min(lo, d[j] - r);
+    hi = std::max(hi, d[j] + r);
+  }
+  // number of eigenvalues below x
+  auto below = [&](double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int j = 0; j < k; ++j) {
+      q = d[j] - x - (j > 0 ? e[j - 1] * e[j - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  auto kth = [&](int want) {   // smallest x with below(x) >= want
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 1e-14 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+      const double mid = 0.5 * (a + b);
+      if (below(mid) >= want) b = mid;
+      else a = mid;
+    }
+    return 0.5 * (a + b);
+  };
+  *lo_out = kth(1);
+  *hi_out = kth(k);
+}
+
 // Step a5: Jacobi PCG (needs prepare()).  Also reports the true relative
 // residual ||rhs - K sol|| / ||rhs|| with the float64 operator.
 static qp_status true_residual(qp_handle h, const double* rhs, const double* sol) {
@@ -433,6 +470,22 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
     au.we = h->we_mv;
   }
   const bool lo = h->vk != VK_F64 && !force64;
+  // CG coefficients for the spectrum estimate (float64 solves: no restarts)
+  const bool spectrum = o.spectrum != 0 && !lo;
+  if (spectrum) {
+    if (h->coef_cap < o.maxit) {
+      if (h->coef) {
+        (void)hipFree(h->coef);
+        auto it = std::find(h->allocs.begin(), h->allocs.end(), (void*)h->coef);
+        if (it != h->allocs.end()) h->allocs.erase(it);
+        h->coef = nullptr;
+      }
+      CHK(dalloc_t(h, &h->coef, 2 * (int64_t)o.maxit));
+      h->coef_cap = o.maxit;
+    }
+    a.coef = h->coef;
+    au.coef = h->coef;
+  }
   const int check = std::max(1, o.check_every);
   int it = 0;
   CHK(read_back(h));
@@ -493,6 +546,19 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
   if (status == QP_ERR_NUMERIC_CODE) inf.status = QP_ERR_NUMERIC;
   if (status == 0) inf.iterations = o.maxit;
   inf.rel_residual = inf.rhs_norm > 0.0 ? std::sqrt(h->hsc[S_RELRES]) / inf.rhs_norm : 0.0;
+  if (spectrum && status != 0 && inf.iterations > 0 && inf.status == QP_OK) {
+    // Lanczos matrix of the preconditioned CG: d_j = 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    // e_j = sqrt(beta_j)/alpha_j
+    const int k = inf.iterations;
+    std::vector<double> ab(2 * (size_t)k);
+    HIPCHK(hipMemcpy(ab.data(), h->coef, sizeof(double) * 2 * k, hipMemcpyDeviceToHost));
+    std::vector<double> d(k), e(k > 1 ? k - 1 : 0);
+    for (int j = 0; j < k; ++j) {
+      d[j] = 1.0 / ab[2 * j] + (j > 0 ? ab[2 * j - 1] / ab[2 * (j - 1)] : 0.0);
+      if (j + 1 < k) e[j] = std::sqrt(ab[2 * j + 1]) / ab[2 * j];
+    }
+    tridiag_extremes(d, e, &inf.lambda_min, &inf.lambda_max);
+  }
   if (lo && (inf.status != QP_OK || !inf.converged || !(inf.rel_residual <= o.tol))) {
     // the reduced-precision operator could not deliver this solve: redo it in float64
     pcg_info again{};
@@ -595,6 +661,7 @@ void qp_default_pcg_options(pcg_options* o) {
   o->maxit = 5000;
   o->check_every = 8;
   o->rr_period = 0;
+  o->spectrum = 0;
 }
 
 void qp_default_ipm_options(ipm_options* o) {
@@ -1296,6 +1363,8 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
       if (opt.log_alpha_lam) opt.log_alpha_lam[li] = h->hsc[S_ALPHA_L];
       if (opt.log_cg_iters) opt.log_cg_iters[li] = pi.iterations;
       if (opt.log_cg_relres) opt.log_cg_relres[li] = pi.rel_residual;
+      if (opt.log_kappa)
+        opt.log_kappa[li] = pi.lambda_min > 0.0 ? pi.lambda_max / pi.lambda_min : 0.0;
     }
     info->rnorm = nr;
     info->primal = h->hsc[S_PRIMAL];

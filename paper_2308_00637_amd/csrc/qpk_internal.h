@@ -290,6 +290,7 @@ struct CgArgs {
   const double* qdiag;
   const double* Cm;
   const double* we;
+  double* coef;              // optional: alpha_k at 2k, beta_k at 2k + 1 (Lanczos)
 };
 hipError_t launch_cg_init(const CgArgs& a, hipStream_t st);
 hipError_t launch_cg_update(const CgArgs& a, hipStream_t st, const KEvents* ev = nullptr);

@@ -1067,6 +1067,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     return;
   }
   const double alpha = rz / pq;
+  if (a.coef && blockIdx.x == 0 && threadIdx.x == 0) a.coef[2 * k] = alpha;
   double rzn = 0.0, rr = 0.0;
   for (; i < a.N; i += stride) {
     a.x[i] = xi + alpha * pi;
@@ -1118,6 +1119,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(CgArgs a) {
     return;
   }
   const double beta = rz_new / rz_old;
+  if (a.coef && blockIdx.x == 0 && threadIdx.x == 0) a.coef[2 * k + 1] = beta;
   for (; i < a.N; i += stride) {
     a.p[i] = zi + beta * pi;
     const int j = i + stride;

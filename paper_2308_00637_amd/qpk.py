@@ -48,12 +48,13 @@ class QpDesc(C.Structure):
 
 class PcgOptions(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
-                ("rr_period", C.c_int32)]
+                ("rr_period", C.c_int32), ("spectrum", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
-                ("rel_residual", C.c_double), ("rhs_norm", C.c_double), ("escalated", C.c_int32)]
+                ("rel_residual", C.c_double), ("rhs_norm", C.c_double), ("escalated", C.c_int32),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double)]
 
 
 class IpmOptions(C.Structure):
@@ -63,7 +64,7 @@ class IpmOptions(C.Structure):
         ("pcg", PcgOptions), ("log_capacity", C.c_int32),
         ("log_mu", _dp), ("log_rnorm", _dp), ("log_primal", _dp), ("log_dual", _dp),
         ("log_compl", _dp), ("log_alpha_x", _dp), ("log_alpha_lam", _dp),
-        ("log_cg_iters", _i32p), ("log_cg_relres", _dp),
+        ("log_cg_iters", _i32p), ("log_cg_relres", _dp), ("log_kappa", _dp),
     ]
 
 
@@ -342,7 +343,7 @@ class QP:
         if log:
             cap = max(int(opts.max_iter), 1)
             logs = {k: np.zeros(cap) for k in ("mu", "rnorm", "primal", "dual", "compl",
-                                               "alpha_x", "alpha_lam", "cg_relres")}
+                                               "alpha_x", "alpha_lam", "cg_relres", "kappa")}
             logs["cg_iters"] = np.zeros(cap, dtype=np.int32)
             opts.log_capacity = cap
             for k, a in logs.items():

@@ -1,0 +1,62 @@
+"""Condition number diagnostic (Section 5.3): the extreme eigenvalues of the
+Jacobi-preconditioned doubly augmented matrix, estimated on the GPU from the
+CG coefficients (Ritz values of the Lanczos matrix CG builds implicitly),
+against the oracle's dense eigenvalues at the same state.  Ritz values lie
+inside the spectrum and approach its ends as CG converges."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_00637_amd import workloads as W
+from tests.helpers import random_state, to_masked
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "general_dense": lambda: W.random_bounded_qp(1, 37, 29, 2, 11),
+    "rt_ptwp": lambda: W.rt_qp(5, 700, 61, 0.08, 23, maxdose=0.6),
+    "quasi_newton_mixed_w": lambda: W.qn_rt(6, 300, 12, 15),
+}
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_ritz_values_bracket_inside_the_dense_spectrum(case):
+    from paper_2308_00637_amd.qpk import QP, default_pcg_options
+    spec = CASES[case]()
+    prob = O.from_spec(spec)
+    qp = QP(spec)
+    st = random_state(prob, np.random.default_rng(42), 0.5)
+    mu = 0.37
+    x, lam, s = to_masked(prob, st)
+    qp.set_state(dev(x), dev(lam), dev(s), mu)
+    rhs, _ = qp.newton_rhs()
+    _, info = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-10, spectrum=1))
+    lo, hi = O.jacobi_spectrum(prob, st, mu)
+    print(f"{case}: its={info.iterations} ritz=[{info.lambda_min:.6g}, {info.lambda_max:.6g}] "
+          f"dense=[{lo:.6g}, {hi:.6g}]", flush=True)
+    assert info.converged == 1
+    assert lo * (1 - 1e-9) <= info.lambda_min <= info.lambda_max <= hi * (1 + 1e-9)
+    # converged to 1e-10: the extreme Ritz values have found the spectrum's ends
+    assert info.lambda_max >= 0.99 * hi
+    assert info.lambda_min <= 1.1 * lo
+
+
+def test_ipm_logs_kappa_per_newton_system():
+    from paper_2308_00637_amd.qpk import QP, default_ipm_options
+    spec = CASES["rt_ptwp"]()
+    prob = O.from_spec(spec)
+    opts = default_ipm_options()
+    opts.pcg.spectrum = 1
+    out = QP(spec).solve(opts, log=True)
+    kap = out["log"]["kappa"]
+    print("kappa per IPM iteration:", np.array2string(kap, precision=3), flush=True)
+    assert out["info"].result == 0
+    assert np.all(np.isfinite(kap)) and np.all(kap >= 1.0)
+    # the first Newton system is at the default start point with mu = 1
+    lo, hi = O.jacobi_spectrum(prob, O.initial_point(prob), 1.0)
+    assert kap[0] <= hi / lo * (1 + 1e-9) and kap[0] >= 0.5 * hi / lo

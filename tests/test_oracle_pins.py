@@ -338,3 +338,32 @@ def test_adjoint_matches_central_differences_on_centered_solves():
         setattr(sm_, name, getattr(base, name) - h * v)
         fd = (L(solve_at(sp_)) - L(solve_at(sm_))) / (2 * h)
         assert abs(fd - grad @ v) <= 1e-4 * max(1e-3, abs(fd)), (name, fd, grad @ v)
+
+
+def test_jacobi_spectrum_of_a_diagonal_system_is_one():
+    """Box-only separable QP: K is diagonal, so diag(K)^-1 K = I."""
+    n = 9
+    spec = W.QPSpec(n=n, c=np.linspace(-1, 1, n), h_kind="dense", H=np.diag(np.linspace(1, 3, n)),
+                    lx=-np.ones(n), ux=np.ones(n))
+    prob = O.from_spec(spec)
+    st = random_state(prob, np.random.default_rng(1), 0.5)
+    lo, hi = O.jacobi_spectrum(prob, st, 0.3)
+    assert lo == pytest.approx(1.0, abs=1e-14) and hi == pytest.approx(1.0, abs=1e-14)
+
+
+def test_jacobi_spectrum_two_by_two_closed_form():
+    """One variable, one lower-bounded row a x >= l: K = [[k11, a], [a, d]] with
+    k11 = h + 2 a^2 / d and d = s / lam, so diag(K)^-1 K has eigenvalues
+    1 -+ |a| / sqrt(k11 d), whatever h, a, s, lam are."""
+    h, a = 2.5, 1.7
+    spec = W.QPSpec(n=1, c=np.array([0.3]), h_kind="dense", H=np.array([[h]]),
+                    A=np.array([[a]]), lA=np.array([-1.0]), uA=np.array([np.inf]))
+    prob = O.from_spec(spec)
+    st = random_state(prob, np.random.default_rng(2), 0.5)
+    d = st.s_lA[0] / st.lam_lA[0]
+    k11 = h + 2.0 * a * a / d
+    off = abs(a) / np.sqrt(k11 * d)
+    lo, hi = O.jacobi_spectrum(prob, st, 0.7)
+    assert lo == pytest.approx(1.0 - off, rel=1e-13) and hi == pytest.approx(1.0 + off, rel=1e-13)
+    c = O.condition_numbers(prob, st, 0.7)
+    assert c["kappa_jacobi"] == pytest.approx((1.0 + off) / (1.0 - off), rel=1e-12)
