@@ -275,6 +275,62 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
   const int ng = gridDim.x * (kBlock / LPR);
   const int n = a.n, m = a.m, me = a.me, k = a.k;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  // Products with a low-rank H and no stored segments (the SVM form): four
+  // rows per group in flight, their epilogue operands read with them.
+  bool rows_done = false;
+  if constexpr (MODE == X_MATVEC) {
+    if (!val && k > 0) {
+      rows_done = true;
+      constexpr int R = 4;
+      using LT = decltype(ldv(U, 0));
+      for (int j0 = gid; j0 < n; j0 += R * ng) {
+        Acc acc[R];
+        double vj[R], qd[R], ce[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int j = j0 + r * ng;
+          acc[r] = 0;
+          vj[r] = qd[r] = ce[r] = 0.0;
+          if (j < n) {
+            const int64_t base = static_cast<int64_t>(j) * k;
+            if ((k & 1) == 0) {
+              // even k: rows start pair-aligned, one 16-byte (float64) load per pair
+#pragma unroll 2
+              for (int l = 2 * lane; l < k; l += 2 * LPR) {
+                LT ux, uy;
+                ldv2(U, base + l, ux, uy);
+                acc[r] += static_cast<Acc>(ux) * static_cast<Acc>(a.g[l]);
+                acc[r] += static_cast<Acc>(uy) * static_cast<Acc>(a.g[l + 1]);
+              }
+            } else {
+#pragma unroll 4
+              for (int l = lane; l < k; l += LPR) acc[r] += ldv(U, base + l) * static_cast<Acc>(a.g[l]);
+            }
+            if (lane == 0) {
+              vj[r] = a.v[j];
+              qd[r] = a.qdiag[j];
+              for (int e = 0; e < me; ++e) ce[r] += a.Cm[static_cast<int64_t>(e) * n + j] * a.we[e];
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = group_sum<LPR>(acc[r]);
+        if (lane == 0) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int j = j0 + r * ng;
+            if (j < n) {
+              double y = static_cast<double>(acc[r]) + ce[r];
+              y += qd[r] * vj[r];
+              a.y[j] = y;
+              p0 += vj[r] * y;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (!rows_done)
   for (int j = gid; j < n; j += ng) {
     Acc acc = 0, acc2 = 0;
     if (val) {
@@ -402,9 +458,9 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
 // ------------------------------------------------ matvec epilogues
 // Matvec epilogues shared by the PCG passes.
 // Row epilogue of the PCG matvec (R_MATVEC): P rows give u = w t; A rows give
-// the lam-part of K v and wA = w_l - w_u.  Returns the row's p_lam . q_lam.
-// Returns this row's term of v_lam . (K v)_lam, plus with a.xdot its term of
-// v_x . (K v)_x: v_x . P^T u = sum_v t_v u_v and v_x . A^T wA = sum_i t_i wA_i.
+// the lam-part of K v and wA = w_l - w_u.  Returns this row's term of
+// v_lam . (K v)_lam, plus with a.xdot its term of v_x . (K v)_x:
+// v_x . P^T u = sum_v t_v u_v and v_x . A^T wA = sum_i t_i wA_i.
 __device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row, double td) {
   if (row < a.p_rows) {
     const double uv = a.w[row] * td;
@@ -726,6 +782,40 @@ __global__ __launch_bounds__(kBlock) void k_ts_reduce(TsArgs a) {
   const int j1 = min(a.n, j0 + a.chunk);
   double* out = a.part + static_cast<int64_t>(blockIdx.x) * KW;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if ((a.k & 1) == 0) {
+    // even k: lane l owns columns 2l, 2l+1 of each 128-column tile, one
+    // 16-byte (float64) load per row, so a wave reads 128 values of a row
+    using LT = decltype(ldv(U, 0));
+    __shared__ double red2[2 * kBlock];
+    for (int c0 = 0; c0 < a.k; c0 += 128) {
+      const int c = c0 + 2 * lane;
+      Acc s0 = 0, s1 = 0;
+      if (c < a.k) {
+#pragma unroll 4
+        for (int j = j0 + wv; j < j1; j += kBlock / 64) {
+          LT ux, uy;
+          ldv2(U, static_cast<int64_t>(j) * a.k + c, ux, uy);
+          const Acc vj = static_cast<Acc>(a.v[j]);
+          s0 += static_cast<Acc>(ux) * vj;
+          s1 += static_cast<Acc>(uy) * vj;
+        }
+      }
+      red2[2 * threadIdx.x] = static_cast<double>(s0);
+      red2[2 * threadIdx.x + 1] = static_cast<double>(s1);
+      __syncthreads();
+      if (wv == 0 && c < a.k) {
+        double t0 = red2[2 * lane], t1 = red2[2 * lane + 1];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) {
+          t0 += red2[2 * (w * 64 + lane)];
+          t1 += red2[2 * (w * 64 + lane) + 1];
+        }
+        out[c] = t0;
+        out[c + 1] = t1;
+      }
+      __syncthreads();
+    }
+  } else
   for (int c0 = 0; c0 < a.k; c0 += 64) {
     const int c = c0 + lane;
     Acc acc = 0;
