@@ -559,7 +559,22 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
     }
     tridiag_extremes(d, e, &inf.lambda_min, &inf.lambda_max);
   }
-  if (lo && (inf.status != QP_OK || !inf.converged || !(inf.rel_residual <= o.tol))) {
+  bool escalate = false;
+  if (lo) {
+    if (inf.status != QP_OK || (inf.converged && !(inf.rel_residual <= o.tol))) {
+      escalate = true;   // breakdown, or a converged recurrence the operator cannot honour
+    } else if (!inf.converged) {
+      // Stopped at the iteration cap, as float64 solves of hard systems do too
+      // (the method then goes on with the iterate).  Redo it in float64 only
+      // when the reduced operator, not the iteration budget, limited it: its
+      // float64 residual well above the recurrence residual the PCG reached.
+      HIPCHK(launch_finish_sum(h->part + P_RR * kGridMax, h->g_vec, h->sc + S_RECUR, h->st));
+      CHK(read_back(h));
+      const double recur = inf.rhs_norm > 0.0 ? std::sqrt(h->hsc[S_RECUR]) / inf.rhs_norm : 0.0;
+      escalate = !(inf.rel_residual <= 10.0 * recur);
+    }
+  }
+  if (escalate) {
     // the reduced-precision operator could not deliver this solve: redo it in float64
     pcg_info again{};
     const qp_status s2 = run_pcg(h, rhs, sol, o, &again, true);

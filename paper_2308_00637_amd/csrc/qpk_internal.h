@@ -202,7 +202,7 @@ enum PartRegion : int {
 // Device scalars (double) and flags (int).
 enum Scalar : int {
   S_ALPHA_X = 0, S_ALPHA_L, S_NORM, S_PRIMAL, S_DUAL, S_COMPL, S_RHSNORM,
-  S_OBJ, S_RELRES, S_COUNT
+  S_OBJ, S_RELRES, S_RECUR, S_COUNT
 };
 enum Flag : int { F_DONE = 0, F_CNT, F_STATUS, F_ITERS, F_BAD, F_COUNT };
 
