@@ -203,10 +203,11 @@ const char* qp_last_error(qp_handle h);
  * Launch-shape overrides, read here from the environment (for tuning and
  * tests; the defaults are the measured best): QPK_CHUNK_COLS_R / _X (columns
  * per LDS chunk of the row / column side, 1024..20224), QPK_LPR_R / _X (lanes
- * per row, 4..64; changes the order of a row's summation), QPK_KV_R / _X (0:
- * chunk staged through registers, 1: straight into LDS), QPK_ALTERNATE (0:
- * every product walks rows first to last), QPK_XCD_MAP (0: work item i on
- * block i).  Apart from QPK_LPR_*, none changes the result of a product. */
+ * per row, 4..64), QPK_KV_R / _X (0: chunk staged through registers, 1:
+ * straight into LDS), QPK_ALTERNATE (0: every product walks rows first to
+ * last), QPK_XCD_MAP (0: work item i on block i).  QPK_KV_*, QPK_ALTERNATE
+ * and QPK_XCD_MAP leave K v bitwise unchanged; chunk widths and lanes per row
+ * change the order in which a row is summed. */
 qp_status qp_create(const qp_desc* d, void* stream, qp_handle* out);
 void qp_destroy(qp_handle h);
 qp_status qp_set_stream(qp_handle h, void* stream);
