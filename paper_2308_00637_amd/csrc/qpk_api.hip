@@ -2,7 +2,8 @@
 // once (qp_create), then drives the kernels of qpk_kernels.hip for each step
 // of Algorithm 1 (Section 3.2).  Host code only launches kernels, reads back a
 // few scalars per IPM iteration and polls one stop flag during PCG; all
-// arithmetic of the method runs on the GPU.
+// arithmetic of the method runs on the GPU (the host only turns the CG
+// coefficients into the optional spectrum estimate).
 #include "qpk_internal.h"
 #include "../../include/qpk.h"
 

@@ -161,7 +161,8 @@ hipError_t launch_ts_reduce(int vk, const TsArgs& a, int grid, hipStream_t st,
 // (chunk, first row, end row), copies that chunk of the gathered vector into
 // LDS and reduces its rows from there.  With one chunk the row epilogue runs in
 // place; otherwise per-chunk partial sums are written and an epilogue kernel
-// adds them in chunk order.
+// adds them in chunk order (in a PCG iteration on a single-chunk row side,
+// k_cg_update adds the column side's itself).
 constexpr int kChunkBlock = 1024;                 // threads per block
 constexpr int kChunkCols = 20224;                 // most float64 values per LDS chunk
 struct ChunkArgs {
