@@ -272,6 +272,35 @@ def cpu_baseline(spec, iters):
                       f"of the same workload; {dt:.1f} s"}
 
 
+def stream_rates(nbytes, reps=20):
+    """Plain device copy and read (torch's copy and sum) of the dominant
+    kernel's working-set size, timed with events on the current stream: the
+    measured bandwidth beside the nominal peak."""
+    import torch
+    n = max(1, int(nbytes) // 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+        a.sum()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        a.sum()
+    ev[3].record()
+    torch.cuda.synchronize()
+    copy_s = ev[0].elapsed_time(ev[1]) / 1e3 / reps
+    read_s = ev[2].elapsed_time(ev[3]) / 1e3 / reps
+    del a, b
+    return {"bytes": 8 * n, "copy_GBs": 2 * 8 * n / copy_s / 1e9, "read_GBs": 8 * n / read_s / 1e9,
+            "how": "torch copy_ (read + write counted) and sum (read) of a float64 tensor "
+                   "of this many bytes, mean of 20 after 3 warm-up"}
+
+
 def main():
     args = parse()
     if args.summarize_stats:
@@ -353,6 +382,8 @@ def main():
                          "avg_us": per_it * 1e6, "bytes": by, "GBs": by / per_it / 1e9}
     dom = max(kern, key=lambda c: kern[c]["avg_us"])
     d = kern[dom]
+    with torch.cuda.stream(stream):
+        rates = stream_rates(d["bytes"])
     per_iter_us = sum(v["avg_us"] for v in kern.values())
     traffic = stored_traffic(args.workload, args.precision, dom)
     result = {
@@ -384,7 +415,9 @@ def main():
                      "unit": "GB/s", "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_us": d["avg_us"], "dispatch_avg_us": d["dispatch_avg_us"],
                      "algorithmic_bytes_per_launch": d["bytes"],
-                     "launches_timed": d["launches_timed"]},
+                     "launches_timed": d["launches_timed"],
+                     "measured_stream": rates, "frac_of_copy": d["GBs"] / rates["copy_GBs"],
+                     "frac_of_read": d["GBs"] / rates["read_GBs"]},
         "kernels": kern,
         "layout": lay,
         "copy_calibration_bytes": calib,
