@@ -545,6 +545,16 @@ __device__ __forceinline__ void ldv2b(const uint16_t*, __amdgpu_buffer_rsrc_t r,
   y = __uint_as_float(u & 0xffff0000u);
 }
 
+// This thread's lane in its wave, recomputed where it is called: the rare
+// rows longer than one batch take their lane offsets from it, so the column
+// pass (held to 64 VGPRs) need not keep them live across the row loop, which
+// had cost three spilled registers per thread.
+__device__ __forceinline__ int lane_of_wave() {
+  int r;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(r));
+  return r;
+}
+
 // Kernel variants: KV 0 stages the chunk through registers (16-byte loads,
 // all issued at once), KV 1 with direct global-to-LDS loads (no registers
 // held, so a half-LDS chunk pass fits 64 VGPRs and two blocks share a CU).
@@ -585,10 +595,10 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
   using LT = decltype(ldv(val, 0));          // loaded value type
 
   // the pairs of one batch starting at entry `base` of a segment ending at `end`
-  auto load_batch = [&](int base, int end, uint32_t* cc, LT* vx, LT* vy) {
+  auto load_batch = [&](int base, int end, uint32_t* cc, LT* vx, LT* vy, int ln) {
 #pragma unroll
     for (int k = 0; k < PP; ++k) {
-      const int q = base + 2 * (lane + k * LPR);
+      const int q = base + 2 * (ln + k * LPR);
       const bool ok = q < end;
       cc[k] = __builtin_amdgcn_raw_buffer_load_b32(rcol, ok ? 2u * q : kOob, 0, 0);
       ldv2b(val, rval, ok ? static_cast<uint32_t>(sizeof(T)) * q : kOob, vx[k], vy[k]);
@@ -639,7 +649,7 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
   bounds(2, b2, e2);
   uint32_t cc[PP], cc1[PP];
   LT vx[PP], vy[PP], vx1[PP], vy1[PP];
-  load_batch(beg, end, cc, vx, vy);
+  load_batch(beg, end, cc, vx, vy, lane);
   if constexpr (DMA) {
     __builtin_amdgcn_s_waitcnt(0);   // LDS-direct loads are counted as vector loads
   } else {
@@ -657,7 +667,7 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
     const int row = row_of(kr);
     int b3, e3;
     bounds(kr + 3, b3, e3);
-    load_batch(b1, e1, cc1, vx1, vy1);
+    load_batch(b1, e1, cc1, vx1, vy1, lane);
     Acc t = 0;
 #pragma unroll
     for (int k = 0; k < PP; ++k) {
@@ -667,7 +677,7 @@ __device__ __forceinline__ void chunked_body(const ChunkArgs& b, const RowArgs& 
     for (int base = beg + SPAN; base < end; base += SPAN) {   // rows longer than one batch
       uint32_t c2[PP];
       LT x[PP], y[PP];
-      load_batch(base, end, c2, x, y);
+      load_batch(base, end, c2, x, y, lane_of_wave() & (LPR - 1));
 #pragma unroll
       for (int k = 0; k < PP; ++k) {
         t += static_cast<Acc>(x[k]) * static_cast<Acc>(lds[c2[k] & 0xffffu]);
