@@ -15,6 +15,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace qpk;
@@ -78,6 +79,10 @@ struct qp_handle_s {
   bool alternate = true;                 // alternate the row direction of the blocked passes
   int64_t n_matvec = 0;                  // blocked K v products so far
   double* uw = nullptr;  // [u (p_rows) | wA (m)] for the PCG matvec
+  // Blocked passes over P alone when every row of A repeats its own row of P:
+  // twin[v] = the A row that repeats P row v, or -1
+  bool fold_a = false;
+  int32_t* twin = nullptr;
   double* coef = nullptr;  // CG alpha/beta record (spectrum estimates), 2 * coef_cap
   int coef_cap = 0;
   std::vector<void*> allocs;
@@ -347,6 +352,7 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     a.vl = h->m > 0 ? v + h->n : v;
     a.dl = h->dl; a.yl = y + h->n;
     a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done;
+    if (h->fold_a) a.twin = h->twin;
     if (fuse && pcg_fuses_epilogue(h)) {
       a.xdot = 1;
       a.qdiag = h->qdiag;
@@ -714,6 +720,48 @@ const char* qp_last_error(qp_handle h) { return h ? h->err.c_str() : g_create_er
 // kChunkCols with uint16 in-chunk offsets, stored chunk-major, and cut each
 // chunk's rows into work items of about equal entry counts so that all items
 // fit one wave of blocks (one block per CU, 256 CUs).
+// Pairs every row of A with a row of P holding the same columns and values
+// (bit for bit), each P row serving at most one A row.  Returns false, with
+// twin untouched, unless every row of A finds one.
+static bool match_twins(int64_t p_rows, const std::vector<int64_t>& prp, const int32_t* pcol,
+                        const double* pval, int64_t m, const std::vector<int64_t>& arp,
+                        const std::vector<int32_t>& acol, const std::vector<double>& aval,
+                        std::vector<int32_t>& twin) {
+  auto row_hash = [](const int32_t* c, const double* v, int64_t len) {
+    uint64_t x = 1469598103934665603ull ^ (uint64_t)len;
+    for (int64_t q = 0; q < len; ++q) {
+      uint64_t b;
+      std::memcpy(&b, &v[q], 8);
+      x = (x ^ (uint64_t)(uint32_t)c[q]) * 1099511628211ull;
+      x = (x ^ b) * 1099511628211ull;
+    }
+    return x;
+  };
+  std::unordered_multimap<uint64_t, int64_t> byhash;
+  byhash.reserve((size_t)p_rows);
+  for (int64_t v = 0; v < p_rows; ++v)
+    byhash.emplace(row_hash(pcol + prp[v], pval + prp[v], prp[v + 1] - prp[v]), v);
+  std::vector<int32_t> t((size_t)p_rows, -1);
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t len = arp[i + 1] - arp[i];
+    const int32_t* c = acol.data() + arp[i];
+    const double* v = aval.data() + arp[i];
+    auto range = byhash.equal_range(row_hash(c, v, len));
+    int64_t found = -1;
+    for (auto it = range.first; it != range.second && found < 0; ++it) {
+      const int64_t r = it->second;
+      if (t[(size_t)r] >= 0 || prp[r + 1] - prp[r] != len) continue;
+      if (std::memcmp(pcol + prp[r], c, 4 * (size_t)len) == 0 &&
+          std::memcmp(pval + prp[r], v, 8 * (size_t)len) == 0)
+        found = r;
+    }
+    if (found < 0) return false;
+    t[(size_t)found] = (int32_t)i;
+  }
+  twin.swap(t);
+  return true;
+}
+
 static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
                                const std::vector<int32_t>& col, const std::vector<double>& val,
                                int ncols, int cw_default, int kv_default, bool row_side,
@@ -997,6 +1045,16 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
     }
   }
 
+  // Rows of A that repeat rows of P (the radiation-therapy form: the max-dose
+  // rows are rows of the dose matrix).  When every row of A has its own twin,
+  // the blocked passes hold P alone (QPK_FOLD_A=0 keeps A in them).
+  std::vector<int32_t> twin;
+  if (want_ck_x && p_rows > 0 && m > 0) {
+    const char* e = std::getenv("QPK_FOLD_A");
+    if (!(e && std::atoi(e) == 0))
+      h->fold_a = match_twins(p_rows, prp, pcol, pval, m, arp, acol, aval, twin);
+  }
+
   // Launch shapes
   const double avg_r = h->nRP > 0 ? (double)h->nnz_rp / h->nRP : 0.0;
   const double avg_x = (double)acc / n + (double)k;
@@ -1026,12 +1084,34 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   // epilogue then runs in place), staged through registers.  Column side:
   // half-LDS chunks staged straight into LDS, two blocks per CU (both
   // measured fastest on the radiation-therapy workload).
-  if (h->nRP > 0)
-    CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, true, "QPK_CHUNK_COLS_R",
+  if (h->fold_a) {
+    // row side: the P rows of RP; column side: XS without its A segments
+    const std::vector<int32_t> rrp_p(rrp.begin(), rrp.begin() + p_rows + 1);
+    std::vector<int32_t> xrp_p(n + 1), scol_p;
+    std::vector<double> xval_p;
+    scol_p.reserve((size_t)pnnz);
+    xval_p.reserve((size_t)pnnz);
+    for (int64_t j = 0; j < n; ++j) {
+      xrp_p[j] = (int32_t)scol_p.size();
+      for (int64_t q = xs1[j]; q < xs2[j]; ++q) {
+        scol_p.push_back(scol[q]);
+        xval_p.push_back(xval[q]);
+      }
+    }
+    xrp_p[n] = (int32_t)scol_p.size();
+    CHK(build_chunked(h, h->ck_r, rrp_p, rcol, rval, (int)n, kChunkCols, 0, true, "QPK_CHUNK_COLS_R",
                       "QPK_LPR_R", "QPK_KV_R"));
-  if (want_ck_x)
-    CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1, false,
+    CHK(build_chunked(h, h->ck_x, xrp_p, scol_p, xval_p, (int)p_rows, kChunkCols / 2, 1, false,
                       "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
+    CHK(upload(h, &h->twin, twin.data(), (int64_t)twin.size()));
+  } else {
+    if (h->nRP > 0)
+      CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, true, "QPK_CHUNK_COLS_R",
+                        "QPK_LPR_R", "QPK_KV_R"));
+    if (want_ck_x)
+      CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1, false,
+                        "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
+  }
   if (const char* e = std::getenv("QPK_ALTERNATE")) h->alternate = std::atoi(e) != 0;
   h->g_epi_r = grid_cap(std::max<int64_t>(h->nRP, 1), kBlock, kGridMax);
   h->g_epi_x = grid_cap(n, kBlock, kGridMax);
@@ -1509,7 +1589,8 @@ qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
     return k.nnz * (vb + 2) + 4 * (int64_t)k.nchunk * (k.nrows + 1);
   };
   if (row_bytes)
-    *row_bytes = h->ck_r.on ? ck_bytes(h->ck_r) : h->nnz_rp * (vb + 4) + 4 * (int64_t)(h->nRP + 1);
+    *row_bytes = h->ck_r.on ? ck_bytes(h->ck_r) + (h->fold_a ? 4 * (int64_t)h->p_rows : 0)
+                            : h->nnz_rp * (vb + 4) + 4 * (int64_t)(h->nRP + 1);
   if (col_bytes)
     *col_bytes = h->ck_x.on ? ck_bytes(h->ck_x) : h->nnz_xs * (vb + 4) + 12 * (int64_t)h->n + 4;
   if (dense_bytes) *dense_bytes = (int64_t)h->n * h->k * vb;

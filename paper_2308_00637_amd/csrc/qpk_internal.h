@@ -77,6 +77,10 @@ struct RowArgs {
   const double* qdiag;       // n
   const double* Cm;          // me*n row-major
   const double* we;          // me
+  // R_MATVEC / CE_ROW on a blocked row side that holds P alone: per P row,
+  // the row of A that repeats it (or -1).  Its A-row epilogue runs on the P
+  // row's dot, and u then carries u + wA for the column pass.
+  const int32_t* twin;
 };
 
 struct ColArgs {

@@ -457,17 +457,10 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
 
 // ------------------------------------------------ matvec epilogues
 // Matvec epilogues shared by the PCG passes.
-// Row epilogue of the PCG matvec (R_MATVEC): P rows give u = w t; A rows give
-// the lam-part of K v and wA = w_l - w_u.  Returns this row's term of
-// v_lam . (K v)_lam, plus with a.xdot its term of v_x . (K v)_x:
-// v_x . P^T u = sum_v t_v u_v and v_x . A^T wA = sum_i t_i wA_i.
-__device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row, double td) {
-  if (row < a.p_rows) {
-    const double uv = a.w[row] * td;
-    a.u[row] = uv;
-    return a.xdot ? td * uv : 0.0;
-  }
-  const int i = row - a.p_rows, me = a.me, m = a.m;
+// Epilogue of A row i with dot td: its y_lam entries and wA_i (also returned
+// in wa); returns its term of v_lam . (K v)_lam, plus with a.xdot t_i wA_i.
+__device__ __forceinline__ double a_row_epilogue(const RowArgs& a, int i, double td, double& wa) {
+  const int me = a.me, m = a.m;
   const bool hl = has_lo(a.lA[i]), hu = has_hi(a.uA[i]);
   const double vlo = a.vl[me + i], vup = a.vl[me + m + i];
   const double dlo = a.dl[me + i], dup = a.dl[me + m + i];
@@ -475,9 +468,36 @@ __device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row,
   const double yup = (hu ? -td : 0.0) + dup * vup;
   a.yl[me + i] = ylo;
   a.yl[me + m + i] = yup;
-  const double wa = (hl ? 2.0 * td / dlo + vlo : 0.0) - (hu ? -2.0 * td / dup + vup : 0.0);
+  wa = (hl ? 2.0 * td / dlo + vlo : 0.0) - (hu ? -2.0 * td / dup + vup : 0.0);
   a.wA[i] = wa;
   return vlo * ylo + vup * yup + (a.xdot ? td * wa : 0.0);
+}
+
+// Row epilogue of the PCG matvec (R_MATVEC): P rows give u = w t; A rows give
+// the lam-part of K v and wA = w_l - w_u.  Returns this row's term of
+// v_lam . (K v)_lam, plus with a.xdot its term of v_x . (K v)_x:
+// v_x . P^T u = sum_v t_v u_v and v_x . A^T wA = sum_i t_i wA_i.
+// With a.twin, a P row that an A row repeats also runs that A row's epilogue
+// on its own dot, and stores u + wA: the column pass, which then holds P^T
+// alone, multiplies by it (P^T u + A^T wA = P^T (u + S wA), S the twin map).
+__device__ __forceinline__ double row_matvec_epilogue(const RowArgs& a, int row, double td) {
+  if (row < a.p_rows) {
+    const double uv = a.w[row] * td;
+    double dot = a.xdot ? td * uv : 0.0;
+    double ut = uv;
+    if (a.twin) {
+      const int i = a.twin[row];
+      if (i >= 0) {
+        double wa;
+        dot += a_row_epilogue(a, i, td, wa);
+        ut += wa;
+      }
+    }
+    a.u[row] = ut;
+    return dot;
+  }
+  double wa;
+  return a_row_epilogue(a, row - a.p_rows, td, wa);
 }
 
 // Column epilogue of the PCG matvec (X_MATVEC); returns v_j y_j.

@@ -5,7 +5,11 @@ max-dose rows > 10,112 columns per column-side chunk; both last chunks have
 odd width), so every PCG product runs the per-chunk partial kernels and both
 epilogues.  Against the oracle's
 matrix-free functions, and against each other: the staging variants and the
-two row directions change no arithmetic, so their products agree bitwise."""
+two row directions change no arithmetic, so their products agree bitwise.  Every max-dose row of A repeats a row of P,
+so by default both passes hold P alone (the A-row epilogues run on the twin
+P rows' dots); QPK_FOLD_A=0 keeps A in both passes, and the two must agree to
+rounding."""
+import dataclasses
 import os
 
 import numpy as np
@@ -32,7 +36,7 @@ def dev(a):
 
 def make_qp(spec, env):
     from paper_2308_00637_amd.qpk import QP
-    keys = ("QPK_KV_R", "QPK_KV_X", "QPK_ALTERNATE")
+    keys = ("QPK_KV_R", "QPK_KV_X", "QPK_ALTERNATE", "QPK_FOLD_A")
     old = {k: os.environ.get(k) for k in keys}
     try:
         for k in keys:
@@ -103,3 +107,51 @@ def test_wide_ipm_solve_kkt_by_oracle_function(wide):
     kkt = O.stacked_norm(O.residuals(prob, gst, info.mu_final))
     assert kkt <= 1e-6 and kkt == pytest.approx(info.rnorm, rel=1e-9)
     assert info.objective == pytest.approx(O.objective(prob, gst.x), rel=1e-12)
+
+
+def test_twin_rows_fold_against_unfolded_and_oracle(wide):
+    spec, prob = wide
+    folded, plain = make_qp(spec, {}), make_qp(spec, {"QPK_FOLD_A": 0})
+    bf, bp = folded.operator_bytes(), plain.operator_bytes()
+    print(f"folded row/col bytes {bf['row_bytes']}/{bf['col_bytes']}, "
+          f"unfolded {bp['row_bytes']}/{bp['col_bytes']}", flush=True)
+    # A (2,000 rows of ~48 entries) is streamed by neither folded pass
+    assert bf["row_bytes"] < bp["row_bytes"] and bf["col_bytes"] < bp["col_bytes"]
+    st = O.initial_point(prob)
+    S = O.index_sets(prob)
+    v = np.random.default_rng(3).standard_normal(prob.n + prob.me + len(S.L) + len(S.U))
+    ref = O.kkt_matvec(prob, st, 1.0, v)
+    ys = []
+    for qp in (folded, plain):
+        qp.init_state(1.0)
+        qp.newton_rhs()
+        y = kkt_from_masked(prob, qp.kkt_matvec(dev(kkt_to_masked(prob, v))).cpu().numpy())
+        assert rel(y, ref) <= 1e-12
+        ys.append(y)
+    assert rel(ys[0], ys[1]) <= 1e-14
+    its = []
+    for qp in (folded, plain):
+        rhs, _ = qp.newton_rhs()
+        sol, info = qp.kkt_pcg_solve(rhs)
+        assert info.converged == 1
+        its.append(info.iterations)
+    print(f"pcg iterations folded {its[0]}, unfolded {its[1]}", flush=True)
+    assert abs(its[0] - its[1]) <= max(2, its[1] // 50)
+
+
+def test_no_fold_when_one_a_row_differs(wide):
+    spec, prob = wide
+    A = spec.A.copy()
+    A.data = A.data.copy()
+    A.data[A.indptr[7]] *= 1.0 + 2.0 ** -40   # row 7 no longer repeats its P row
+    spec2 = dataclasses.replace(spec, A=A, name="rt_wide_one_row_off")
+    prob2 = O.from_spec(spec2)
+    qp, plain = make_qp(spec2, {}), make_qp(spec2, {"QPK_FOLD_A": 0})
+    assert qp.operator_bytes() == plain.operator_bytes()
+    st = O.initial_point(prob2)
+    S = O.index_sets(prob2)
+    v = np.random.default_rng(4).standard_normal(prob2.n + prob2.me + len(S.L) + len(S.U))
+    qp.init_state(1.0)
+    qp.newton_rhs()
+    y = kkt_from_masked(prob2, qp.kkt_matvec(dev(kkt_to_masked(prob2, v))).cpu().numpy())
+    assert rel(y, O.kkt_matvec(prob2, st, 1.0, v)) <= 1e-12
