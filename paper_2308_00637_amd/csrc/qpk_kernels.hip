@@ -276,21 +276,35 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
   const int n = a.n, m = a.m, me = a.me, k = a.k;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
   // Products with a low-rank H and no stored segments (the SVM form): four
-  // rows per group in flight, their epilogue operands read with them.
+  // rows per group in flight.  Lane s of a group keeps the dot of the
+  // group's s-th row; every LPR rows, and after the last, each lane runs the
+  // epilogue of the row it holds, so the stores leave in bursts instead of
+  // one per row between the loads.
   bool rows_done = false;
   if constexpr (MODE == X_MATVEC) {
     if (!val && k > 0) {
       rows_done = true;
       constexpr int R = 4;
       using LT = decltype(ldv(U, 0));
+      int held_n = 0, held_j = 0;
+      double held = 0.0;
+      auto flush = [&]() {
+        if (lane < held_n) {
+          double y = held;
+          for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + held_j] * a.we[e];
+          const double vj = a.v[held_j];
+          y += a.qdiag[held_j] * vj;
+          a.y[held_j] = y;
+          p0 += vj * y;
+        }
+        held_n = 0;
+      };
       for (int j0 = gid; j0 < n; j0 += R * ng) {
         Acc acc[R];
-        double vj[R], qd[R], ce[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int j = j0 + r * ng;
           acc[r] = 0;
-          vj[r] = qd[r] = ce[r] = 0.0;
           if (j < n) {
             const int64_t base = static_cast<int64_t>(j) * k;
             if ((k & 1) == 0) {
@@ -306,28 +320,23 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
 #pragma unroll 4
               for (int l = lane; l < k; l += LPR) acc[r] += ldv(U, base + l) * static_cast<Acc>(a.g[l]);
             }
-            if (lane == 0) {
-              vj[r] = a.v[j];
-              qd[r] = a.qdiag[j];
-              for (int e = 0; e < me; ++e) ce[r] += a.Cm[static_cast<int64_t>(e) * n + j] * a.we[e];
-            }
           }
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = group_sum<LPR>(acc[r]);
-        if (lane == 0) {
+        for (int r = 0; r < R; ++r) acc[r] = group_sum<LPR>(acc[r]);   // butterfly: on every lane
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int j = j0 + r * ng;
-            if (j < n) {
-              double y = static_cast<double>(acc[r]) + ce[r];
-              y += qd[r] * vj[r];
-              a.y[j] = y;
-              p0 += vj[r] * y;
+        for (int r = 0; r < R; ++r) {
+          const int j = j0 + r * ng;
+          if (j < n) {
+            if (lane == held_n) {
+              held = static_cast<double>(acc[r]);
+              held_j = j;
             }
+            if (++held_n == LPR) flush();
           }
         }
       }
+      flush();
     }
   }
   if (!rows_done)
