@@ -205,9 +205,11 @@ const char* qp_last_error(qp_handle h);
  * per LDS chunk of the row / column side, 1024..20224), QPK_LPR_R / _X (lanes
  * per row, 4..64), QPK_KV_R / _X (0: chunk staged through registers, 1:
  * straight into LDS), QPK_ALTERNATE (0: every product walks rows first to
- * last), QPK_XCD_MAP (0: work item i on block i).  QPK_KV_*, QPK_ALTERNATE
- * and QPK_XCD_MAP leave K v bitwise unchanged; chunk widths and lanes per row
- * change the order in which a row is summed. */
+ * last), QPK_XCD_MAP (0: work item i on block i), QPK_FOLD_A (0: keep A in
+ * the blocked passes even when every row of A repeats its own row of P; by
+ * default such an A is folded into P's rows).  QPK_KV_*, QPK_ALTERNATE and
+ * QPK_XCD_MAP leave K v bitwise unchanged; chunk widths, lanes per row and
+ * QPK_FOLD_A change the order in which sums are taken. */
 qp_status qp_create(const qp_desc* d, void* stream, qp_handle* out);
 void qp_destroy(qp_handle h);
 qp_status qp_set_stream(qp_handle h, void* stream);

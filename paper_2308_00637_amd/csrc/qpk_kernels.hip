@@ -275,30 +275,31 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
   const int ng = gridDim.x * (kBlock / LPR);
   const int n = a.n, m = a.m, me = a.me, k = a.k;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  // X_MATVEC: lane s of a group keeps the dot of the group's s-th row; every
+  // LPR rows, and after the last, each lane runs the epilogue of the row it
+  // holds, so the stores leave in bursts instead of one per row between the
+  // loads (21% off U(w g) on a 500k x 128 factor).
+  int held_n = 0, held_j = 0;
+  double held = 0.0;
+  auto flush = [&]() {
+    if (lane < held_n) {
+      double y = held;
+      for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + held_j] * a.we[e];
+      const double vj = a.v[held_j];
+      y += a.qdiag[held_j] * vj;
+      a.y[held_j] = y;
+      p0 += vj * y;
+    }
+    held_n = 0;
+  };
   // Products with a low-rank H and no stored segments (the SVM form): four
-  // rows per group in flight.  Lane s of a group keeps the dot of the
-  // group's s-th row; every LPR rows, and after the last, each lane runs the
-  // epilogue of the row it holds, so the stores leave in bursts instead of
-  // one per row between the loads.
+  // rows per group in flight.
   bool rows_done = false;
   if constexpr (MODE == X_MATVEC) {
     if (!val && k > 0) {
       rows_done = true;
       constexpr int R = 4;
       using LT = decltype(ldv(U, 0));
-      int held_n = 0, held_j = 0;
-      double held = 0.0;
-      auto flush = [&]() {
-        if (lane < held_n) {
-          double y = held;
-          for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + held_j] * a.we[e];
-          const double vj = a.v[held_j];
-          y += a.qdiag[held_j] * vj;
-          a.y[held_j] = y;
-          p0 += vj * y;
-        }
-        held_n = 0;
-      };
       for (int j0 = gid; j0 < n; j0 += R * ng) {
         Acc acc[R];
 #pragma unroll
@@ -336,7 +337,6 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
           }
         }
       }
-      flush();
     }
   }
   if (!rows_done)
@@ -381,17 +381,19 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
         }
       }
     }
-    acc = group_sum<LPR>(acc);
+    acc = group_sum<LPR>(acc);   // butterfly: on every lane
     if constexpr (MODE == X_RHS) acc2 = group_sum<LPR>(acc2);
+    if constexpr (MODE == X_MATVEC) {
+      if (lane == held_n) {
+        held = static_cast<double>(acc);
+        held_j = j;
+      }
+      if (++held_n == LPR) flush();
+      continue;
+    }
     if (lane != 0) continue;
     double y = static_cast<double>(acc);
-    if constexpr (MODE == X_MATVEC) {
-      for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + j] * a.we[e];
-      const double vj = a.v[j];
-      y += a.qdiag[j] * vj;
-      a.y[j] = y;
-      p0 += vj * y;
-    } else if constexpr (MODE == X_RESID) {
+    if constexpr (MODE == X_RESID) {
       const ResOff o(n, m, me);
       const double xj = a.v[j];
       for (int e = 0; e < me; ++e) y += a.Cm[static_cast<int64_t>(e) * n + j] * a.we[e];
@@ -447,6 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
       p0 += xj * (0.5 * y + a.c[j]);
     }
   }
+  if constexpr (MODE == X_MATVEC) flush();
   if constexpr (MODE == X_MATVEC || MODE == X_RESID || MODE == X_OBJ) {
     const double s0 = block_sum(p0);
     double s1 = 0.0, s2 = 0.0;
