@@ -125,12 +125,15 @@ typedef struct {
   int32_t rr_period;         /* reduced precision only: replace r by the float64 residual
                               * rhs - K x every rr_period iterations (search direction kept);
                               * default 0 = only when the stop test fires */
-  int32_t spectrum;          /* 1: estimate the extreme eigenvalues of the Jacobi-
-                              * preconditioned matrix diag(K)^-1 K from the CG coefficients
-                              * (the Lanczos tridiagonal matrix that CG builds implicitly),
-                              * reported in pcg_info; the condition number diagnostic of
-                              * Section 5.3.  Float64 solves without restarts only.
-                              * Default 0 */
+  int32_t spectrum;          /* 1: estimate the extreme eigenvalues of the preconditioned
+                              * matrix (diag(K)^-1 K, or K itself with no_precond = 1) from
+                              * the CG coefficients (the Lanczos tridiagonal matrix that CG
+                              * builds implicitly), reported in pcg_info; the condition
+                              * number diagnostic of Section 5.3.  Float64 solves without
+                              * restarts only.  Default 0 */
+  int32_t no_precond;        /* 1: plain CG (z = r) instead of the Jacobi preconditioner
+                              * z = r / diag(K) of Section 3.1, e.g. to estimate the
+                              * spectrum of K itself.  Default 0 */
 } pcg_options;
 
 typedef struct {
@@ -145,7 +148,8 @@ typedef struct {
                               * iterations then counts both attempts */
   double lambda_min;         /* spectrum = 1: smallest and largest Ritz value of the */
   double lambda_max;         /* CG tridiagonal matrix (inside the spectrum of diag(K)^-1 K,
-                              * converging to its ends); 0 when not estimated */
+                              * or of K with no_precond, converging to its ends); 0 when
+                              * not estimated */
 } pcg_info;
 
 /* Algorithm 1 settings.  gamma of eq. (10); mu is divided by mu_div when the
@@ -172,6 +176,11 @@ typedef struct {
   double* log_cg_relres;
   double* log_kappa;         /* lambda_max / lambda_min of each Newton system (needs
                               * pcg.spectrum = 1), or NULL */
+  double* log_kappa_plain;   /* the same for K itself (no preconditioner), or NULL: each
+                              * Newton system is then also solved by plain CG (spectrum on,
+                              * the pcg tolerance and cap), for this log only (the iterate
+                              * does not use it; its time counts in time_ms, not in
+                              * pcg_time_ms or total_cg_iters).  Float64 handles */
 } ipm_options;
 
 typedef enum { QP_IPM_CONVERGED = 0, QP_IPM_MAX_ITER = 1 } qp_ipm_result;
@@ -295,7 +304,8 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c,
  * `workgroups` (<= 0: 512) workgroups of 1024 threads take instances from a
  * queue, largest first, and each solves its instances start to finish (same
  * steps, readings and defaults as ipm_solve; per-iteration logs are not
- * kept).  infos: HOST array of `count`, each time_ms is the whole launch.
+ * kept; of o->pcg only tol and maxit are read: always Jacobi, no spectrum).
+ * infos: HOST array of `count`, each time_ms is the whole launch.
  * Returns QP_ERR_NOT_SPD / QP_ERR_NUMERIC if an instance stopped on one
  * (the others are still solved).  qp_batch_get_solution copies instance i's
  * iterate (DEVICE pointers, layouts as for a single handle with me = 0). */

@@ -50,6 +50,8 @@ struct qp_handle_s {
   double *wA_mv = nullptr, *wA_res = nullptr, *wA_rhs = nullptr, *jw = nullptr;
   double *we_mv = nullptr, *we_res = nullptr, *we_rhs = nullptr, *te = nullptr, *g = nullptr, *u = nullptr;
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *tmp = nullptr;
+  double* ones = nullptr;   // N ones: the "diagonal" of plain CG (pcg_options::no_precond)
+  double* kap_sol = nullptr;  // solution of the plain CG run for ipm_options::log_kappa_plain
   double *dir = nullptr, *ds_w = nullptr;   // dir = [dx | dlam] (n + me + 2m + 2n)
   double* arhs = nullptr;                    // adjoint right-hand side
   double* valign = nullptr;                  // 16-byte aligned copy of a caller vector
@@ -464,6 +466,13 @@ static qp_status true_residual(qp_handle h, const double* rhs, const double* sol
 static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_options& o,
                          pcg_info* info, bool force64 = false) {
   CgArgs a = cg_args(h, rhs, sol, o);
+  if (o.no_precond) {
+    if (!h->ones) {
+      CHK(dalloc_t(h, &h->ones, h->N()));
+      HIPCHK(launch_fill(h->ones, h->N(), 1.0, h->st));
+    }
+    a.jdiag = h->ones;
+  }
   HIPCHK(launch_cg_init(a, h->st));
   const bool fuse = pcg_fuses_epilogue(h);
   CgArgs au = a;   // k_cg_update's view: q's x-part from the column partials
@@ -684,6 +693,7 @@ void qp_default_pcg_options(pcg_options* o) {
   o->check_every = 8;
   o->rr_period = 0;
   o->spectrum = 0;
+  o->no_precond = 0;
 }
 
 void qp_default_ipm_options(ipm_options* o) {
@@ -1436,6 +1446,17 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
     info->total_cg_iters += pi.iterations;
     if (!pi.converged) info->cg_maxiter_hits++;
     if (pi.escalated) info->cg_escalations++;
+    double kappa_plain = 0.0;
+    if (opt.log_kappa_plain && it - 1 < opt.log_capacity) {
+      // the spectrum of K itself (Section 5.3), from plain CG on the same system
+      if (!h->kap_sol) CHK(dalloc_t(h, &h->kap_sol, h->N()));
+      pcg_options pp = po;
+      pp.no_precond = 1;
+      pp.spectrum = 1;
+      pcg_info pk{};
+      CHK(run_pcg(h, h->rhs, h->kap_sol, pp, &pk));
+      kappa_plain = pk.lambda_min > 0.0 ? pk.lambda_max / pk.lambda_min : 0.0;
+    }
     CHK(run_recover(h, opt.gamma));
     VecArgs v = vec_args(h);
     HIPCHK(launch_update(v, h->dir, h->dir + h->n, h->ds_w, h->sc + S_ALPHA_X, 0.0, 0.0,
@@ -1461,6 +1482,7 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
       if (opt.log_cg_relres) opt.log_cg_relres[li] = pi.rel_residual;
       if (opt.log_kappa)
         opt.log_kappa[li] = pi.lambda_min > 0.0 ? pi.lambda_max / pi.lambda_min : 0.0;
+      if (opt.log_kappa_plain) opt.log_kappa_plain[li] = kappa_plain;
     }
     info->rnorm = nr;
     info->primal = h->hsc[S_PRIMAL];

@@ -48,7 +48,7 @@ class QpDesc(C.Structure):
 
 class PcgOptions(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("check_every", C.c_int32),
-                ("rr_period", C.c_int32), ("spectrum", C.c_int32)]
+                ("rr_period", C.c_int32), ("spectrum", C.c_int32), ("no_precond", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
@@ -65,6 +65,7 @@ class IpmOptions(C.Structure):
         ("log_mu", _dp), ("log_rnorm", _dp), ("log_primal", _dp), ("log_dual", _dp),
         ("log_compl", _dp), ("log_alpha_x", _dp), ("log_alpha_lam", _dp),
         ("log_cg_iters", _i32p), ("log_cg_relres", _dp), ("log_kappa", _dp),
+        ("log_kappa_plain", _dp),
     ]
 
 
@@ -336,14 +337,19 @@ class QP:
         self._check(LIB.qp_take_step(self.h, _dev(dx), _dev(dlam), _dev(ds), float(ax), float(al)))
 
     # Algorithm 1
-    def solve(self, opts: Optional[IpmOptions] = None, log: bool = False, want_state: bool = True):
+    def solve(self, opts: Optional[IpmOptions] = None, log: bool = False, want_state: bool = True,
+              log_kappa_plain: bool = False):
+        """ipm_solve.  log: per-iteration arrays in out["log"]; log_kappa_plain
+        (with log) also solves each Newton system by plain CG to log the
+        condition number of K itself (out["log"]["kappa_plain"])."""
         if opts is None:
             opts = default_ipm_options()
         logs = None
         if log:
             cap = max(int(opts.max_iter), 1)
-            logs = {k: np.zeros(cap) for k in ("mu", "rnorm", "primal", "dual", "compl",
-                                               "alpha_x", "alpha_lam", "cg_relres", "kappa")}
+            keys = ["mu", "rnorm", "primal", "dual", "compl", "alpha_x", "alpha_lam", "cg_relres",
+                    "kappa"] + (["kappa_plain"] if log_kappa_plain else [])
+            logs = {k: np.zeros(cap) for k in keys}
             logs["cg_iters"] = np.zeros(cap, dtype=np.int32)
             opts.log_capacity = cap
             for k, a in logs.items():

@@ -1,14 +1,15 @@
 """Condition number diagnostic (Section 5.3): the extreme eigenvalues of the
-Jacobi-preconditioned doubly augmented matrix, estimated on the GPU from the
-CG coefficients (Ritz values of the Lanczos matrix CG builds implicitly),
-against the oracle's dense eigenvalues at the same state.  Ritz values lie
-inside the spectrum and approach its ends as CG converges."""
+doubly augmented matrix, with the Jacobi preconditioner and without it
+(pcg_options.no_precond), estimated on the GPU from the CG coefficients
+(Ritz values of the Lanczos matrix CG builds implicitly), against the
+oracle's dense eigenvalues at the same state.  Ritz values lie inside the
+spectrum and approach its ends as CG converges."""
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2308_00637_amd import workloads as W
-from tests.helpers import random_state, to_masked
+from tests.helpers import kkt_from_masked, random_state, to_masked
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -60,3 +61,53 @@ def test_ipm_logs_kappa_per_newton_system():
     # the first Newton system is at the default start point with mu = 1
     lo, hi = O.jacobi_spectrum(prob, O.initial_point(prob), 1.0)
     assert kap[0] <= hi / lo * (1 + 1e-9) and kap[0] >= 0.5 * hi / lo
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_plain_cg_ritz_values_and_solution_against_dense_k(case):
+    from paper_2308_00637_amd.qpk import QP, default_pcg_options
+    spec = CASES[case]()
+    prob = O.from_spec(spec)
+    qp = QP(spec)
+    st = random_state(prob, np.random.default_rng(42), 0.5)
+    mu = 0.37
+    x, lam, s = to_masked(prob, st)
+    qp.set_state(dev(x), dev(lam), dev(s), mu)
+    rhs, _ = qp.newton_rhs()
+    sol, info = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-10, spectrum=1, no_precond=1))
+    _, jinfo = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-10))
+    K = O.kkt_dense(prob, st, mu)
+    ev = np.linalg.eigvalsh(K)
+    kap = O.condition_numbers(prob, st, mu)
+    print(f"{case}: plain its={info.iterations} (Jacobi {jinfo.iterations}) "
+          f"ritz=[{info.lambda_min:.6g}, {info.lambda_max:.6g}] dense=[{ev[0]:.6g}, {ev[-1]:.6g}] "
+          f"kappa={kap['kappa']:.3g} kappa_jacobi={kap['kappa_jacobi']:.3g}", flush=True)
+    assert info.converged == 1
+    assert ev[0] * (1 - 1e-9) <= info.lambda_min <= info.lambda_max <= ev[-1] * (1 + 1e-9)
+    assert info.lambda_max >= 0.99 * ev[-1]
+    assert info.lambda_min <= 1.1 * ev[0]
+    # plain CG reaches the same solution (the host copy is in the masked layout)
+    ref = np.linalg.solve(K, O.newton_rhs_doubly(prob, st, mu)[0])
+    got = kkt_from_masked(prob, sol.cpu().numpy())
+    assert np.linalg.norm(got - ref) <= 1e-10 * kap["kappa"] * np.linalg.norm(ref)
+
+
+def test_ipm_logs_kappa_of_k_itself_by_plain_cg():
+    from paper_2308_00637_amd.qpk import QP, default_ipm_options
+    spec = CASES["rt_ptwp"]()
+    prob = O.from_spec(spec)
+    opts = default_ipm_options()
+    opts.pcg.spectrum = 1
+    out = QP(spec).solve(opts, log=True, log_kappa_plain=True)
+    ref = QP(spec).solve(default_ipm_options())
+    kj, kp = out["log"]["kappa"], out["log"]["kappa_plain"]
+    print("kappa (Jacobi):", np.array2string(kj, precision=3), flush=True)
+    print("kappa (plain): ", np.array2string(kp, precision=3), flush=True)
+    # the extra solves leave the method's own path alone
+    assert out["info"].result == 0 and out["info"].iterations == ref["info"].iterations
+    assert out["info"].objective == pytest.approx(ref["info"].objective, rel=1e-10)
+    assert np.all(np.isfinite(kp)) and np.all(kp >= 1.0)
+    # first Newton system: default start point, mu = 1; Ritz estimates from inside the spectrum
+    c = O.condition_numbers(prob, O.initial_point(prob), 1.0)
+    assert 0.5 * c["kappa"] <= kp[0] <= c["kappa"] * (1 + 1e-9)
+    assert 0.5 * c["kappa_jacobi"] <= kj[0] <= c["kappa_jacobi"] * (1 + 1e-9)

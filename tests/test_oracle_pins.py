@@ -367,3 +367,6 @@ def test_jacobi_spectrum_two_by_two_closed_form():
     assert lo == pytest.approx(1.0 - off, rel=1e-13) and hi == pytest.approx(1.0 + off, rel=1e-13)
     c = O.condition_numbers(prob, st, 0.7)
     assert c["kappa_jacobi"] == pytest.approx((1.0 + off) / (1.0 - off), rel=1e-12)
+    # K itself: eigenvalues (k11 + d)/2 -+ sqrt(((k11 - d)/2)^2 + a^2)
+    mid, rad = 0.5 * (k11 + d), np.hypot(0.5 * (k11 - d), a)
+    assert c["kappa"] == pytest.approx((mid + rad) / (mid - rad), rel=1e-11)
