@@ -155,3 +155,41 @@ def test_no_fold_when_one_a_row_differs(wide):
     qp.newton_rhs()
     y = kkt_from_masked(prob2, qp.kkt_matvec(dev(kkt_to_masked(prob2, v))).cpu().numpy())
     assert rel(y, O.kkt_matvec(prob2, st, 1.0, v)) <= 1e-12
+
+
+def _rt_with_rows(P, rows, seed):
+    """A radiation-therapy QP on P whose max-dose rows are the given rows of P."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n_vox, n = P.shape
+    A = sp.csr_matrix(P[rows])
+    return W.QPSpec(n=n, c=np.zeros(n), h_kind="ptwp", P=P, w=np.where(rng.random(n_vox) < 0.1, 10.0, 1.0),
+                    d=rng.uniform(0.0, 1.0, n_vox), A=A, lA=np.full(len(rows), -np.inf),
+                    uA=np.full(len(rows), 0.8), lx=np.zeros(n), ux=np.full(n, np.inf))
+
+
+@pytest.mark.parametrize("kind", ["repeated_a_row", "repeated_p_row"])
+def test_twin_rows_with_repeats(kind):
+    """Two equal rows of A and one such row of P: no fold (each A row needs
+    a twin of its own); two equal rows of P repeated by two rows of A: fold,
+    one twin each.  Either way K v matches the oracle."""
+    import scipy.sparse as sp
+    base = W.rt_qp(21, 3_000, 400, 0.02, 1, name="rt_repeats")
+    P = sp.csr_matrix(base.P)
+    if kind == "repeated_a_row":
+        rows, fold = [5, 9, 9, 40], False
+    else:
+        P = sp.vstack([P, P[[17]]]).tocsr()   # row 3,000 repeats row 17
+        rows, fold = [17, 3_000, 40], True
+    spec = _rt_with_rows(P, rows, 22)
+    prob = O.from_spec(spec)
+    qp, plain = make_qp(spec, {}), make_qp(spec, {"QPK_FOLD_A": 0})
+    bf, bp = qp.operator_bytes(), plain.operator_bytes()
+    assert (bf["col_bytes"] < bp["col_bytes"]) == fold
+    st = O.initial_point(prob)
+    S = O.index_sets(prob)
+    v = np.random.default_rng(6).standard_normal(prob.n + prob.me + len(S.L) + len(S.U))
+    qp.init_state(1.0)
+    qp.newton_rhs()
+    y = kkt_from_masked(prob, qp.kkt_matvec(dev(kkt_to_masked(prob, v))).cpu().numpy())
+    assert rel(y, O.kkt_matvec(prob, st, 1.0, v)) <= 1e-12
