@@ -423,6 +423,9 @@ def main():
         "copy_calibration_bytes": calib,
         "pcg_kernel_us_per_iteration": per_iter_us,
         "pcg_wall_us_per_iteration": solve_s / max(1, total_cg) * 1e6,
+        # the same count over the time inside the PCG solves only (the IPM's
+        # own kernels and host steps excluded); `value` keeps the whole solve
+        "pcg_iters_per_s_inside_pcg": total_cg / max(1e-9, sum(i.pcg_time_ms for i in infos) / 1e3),
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
