@@ -258,14 +258,16 @@ def cpu_baseline(spec, iters):
     rhs, _ = O.newton_rhs_doubly(prob, st, 1.0)
     dg = O.jacobi_diagonal(prob, st, 1.0)
     mv = lambda v: O.kkt_matvec(prob, st, 1.0, v)
-    if iters <= 0:
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):   # one core: BLAS and OpenMP pools held to one thread
+        if iters <= 0:
+            t0 = time.perf_counter()
+            mv(rhs)
+            one = time.perf_counter() - t0
+            iters = int(max(3, min(200, 15.0 / max(one, 1e-6))))
         t0 = time.perf_counter()
-        mv(rhs)
-        one = time.perf_counter() - t0
-        iters = int(max(3, min(200, 15.0 / max(one, 1e-6))))
-    t0 = time.perf_counter()
-    pcg(mv, rhs, dg, tol=1e-300, maxit=iters)
-    dt = time.perf_counter() - t0
+        pcg(mv, rhs, dg, tol=1e-300, maxit=iters)
+        dt = time.perf_counter() - t0
     return {"value": iters / dt, "unit": "PCG iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} iterations of the oracle's Jacobi PCG (matrix-free K v in "
                       f"NumPy/SciPy, float64, single-threaded) on the first Newton system "
