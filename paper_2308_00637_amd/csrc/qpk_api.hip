@@ -862,11 +862,13 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   // entry pairs per lane at up to 8 lanes per row, the others four (see
   // k_chunked): size the group so one batch covers a typical row, the
   // single-chunk row side (the hot one, float64) generously, else about four
-  // entries per lane.
+  // entries per lane.  On that row side 4 lanes of 16 entries, then 16 or
+  // more lanes of 8: for rows of about 100 entries, 16 lanes of 8 measured
+  // 39.9 us against 41.3 us for 8 lanes of 16.
   ck.lpr = pow2_clamp(avg / 4.0, 4, 64);
   if (row_side && nchunk == 1 && h->vk == VK_F64 && ck.kv == 0) {
     ck.lpr = 4;
-    while (ck.lpr < 64 && ck.lpr * (ck.lpr <= 8 ? 16 : 8) < avg) ck.lpr *= 2;
+    while (ck.lpr < 64 && ck.lpr * (ck.lpr <= 4 ? 16 : 8) < avg) ck.lpr *= 2;
   }
   if (const char* e = std::getenv(env_lpr)) ck.lpr = pow2_clamp(std::atof(e), 4, 64);
   if (const char* e = std::getenv("QPK_XCD_MAP")) ck.xcd_map = std::atoi(e) != 0;
