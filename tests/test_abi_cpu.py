@@ -34,6 +34,25 @@ def test_library_loads_and_exports_every_declared_function(qpk):
     assert sorted(qpk.EXPORTS) == names
 
 
+@pytest.mark.parametrize("name", ["PcgOptions", "IpmOptions"])
+def test_option_structs_match_the_library_layout(qpk, name):
+    """The library fills a struct of its own size: a binding struct of
+    another size would be overrun (the bytes after it must stay untouched)
+    or left partly unset."""
+    cls = getattr(qpk, name)
+    size = C.sizeof(cls)
+    buf = (C.c_ubyte * (size + 64))(*([0xAB] * (size + 64)))
+    fill = qpk.LIB.qp_default_pcg_options if name == "PcgOptions" else qpk.LIB.qp_default_ipm_options
+    fill(C.cast(buf, C.POINTER(cls)))
+    assert bytes(buf[size:]) == b"\xab" * 64
+    o = cls.from_buffer(buf)
+    pcg = o if name == "PcgOptions" else o.pcg
+    assert (pcg.tol, pcg.maxit, pcg.check_every, pcg.rr_period, pcg.spectrum, pcg.no_precond) == \
+        (1e-7, 5000, 8, 0, 0, 0)
+    if name == "IpmOptions":
+        assert o.max_iter == 200 and not o.log_kappa and not o.log_kappa_plain
+
+
 def test_default_options_match_the_paper(qpk):
     o = qpk.default_ipm_options()
     assert o.gamma == 0.99 and o.mu0 == 1.0 and o.mu_tol == 1e-6 and o.mu_div == 10.0
