@@ -93,7 +93,13 @@ def from_spec(spec) -> Problem:
         w = np.array(spec.w, dtype=np.float64)
         d = np.array(spec.d, dtype=np.float64)
         Hmul = lambda v: P.T @ (w * (P @ v))
-        Hdense = lambda: (P.T @ sp.diags(w) @ P).toarray()
+        cache = {}
+
+        def Hdense():
+            # formed once per problem (a 20,000 x 20,000 P^T W P takes a minute)
+            if "H" not in cache:
+                cache["H"] = (P.T @ sp.diags(w) @ P).toarray()
+            return cache["H"]
         Hdiag = lambda: np.asarray(P.multiply(P).T @ w).ravel()
         # 1/2 sum_v w_v (P_v x - d_v)^2 = 1/2 x^T P^T W P x - (P^T W d)^T x + const
         p = np.array(spec.c, dtype=np.float64) - P.T @ (w * d)

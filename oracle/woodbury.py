@@ -39,15 +39,22 @@ def schur_direction(prob: Problem, st: State, mu: float, res: Residuals = None):
     _, _, D, r1, r2, qb = reduced_system(prob, st, res, mu, with_Q=False)
     me, nl = prob.me, S.L.size
     Dinv = 1.0 / D
-    M = prob.Hdense() + np.diag(qb)
+    M = np.array(prob.Hdense(), dtype=np.float64)      # a fresh copy: factored in place
+    M[np.diag_indices(prob.n)] += qb
     if me:
         M += prob.C.T @ (prob.C / mu)
     for blk, dsl in ((S.AL, slice(me, me + nl)), (S.AU, slice(me + nl, None))):
         if blk.shape[0]:
-            Bd = blk.toarray() if sp.issparse(blk) else np.asarray(blk)
-            M += Bd.T @ (Dinv[dsl][:, None] * Bd)
+            if sp.issparse(blk):
+                # B^T D^-1 B as a sparse product, added entry by entry
+                T = (blk.T @ sp.diags(Dinv[dsl]) @ blk).tocoo()
+                T.sum_duplicates()
+                M[T.row, T.col] += T.data
+            else:
+                Bd = np.asarray(blk)
+                M += Bd.T @ (Dinv[dsl][:, None] * Bd)
     Bmul, BTmul = _B_ops(prob, S)
-    cf = sla.cho_factor(M, lower=True)
+    cf = sla.cho_factor(M, lower=True, overwrite_a=True)
     dx = sla.cho_solve(cf, r1 + BTmul(Dinv * r2))
     dlam = Dinv * (r2 - Bmul(dx))
     return direction_from_solution(prob, st, res, np.concatenate([dx, dlam]))

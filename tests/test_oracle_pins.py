@@ -370,3 +370,128 @@ def test_jacobi_spectrum_two_by_two_closed_form():
     # K itself: eigenvalues (k11 + d)/2 -+ sqrt(((k11 - d)/2)^2 + a^2)
     mid, rad = 0.5 * (k11 + d), np.hypot(0.5 * (k11 - d), a)
     assert c["kappa"] == pytest.approx((mid + rad) / (mid - rad), rel=1e-11)
+
+
+# ------------------------------------------------ PCG stop rule (Section 5.1)
+def _true_relres(K, rhs, x):
+    """||rhs - K x||_2 / ||rhs||_2 computed here, not taken from the solver."""
+    return float(np.linalg.norm(rhs - K @ x) / np.linalg.norm(rhs))
+
+
+def test_pcg_stops_at_first_iterate_below_tol_on_the_unpreconditioned_residual():
+    """Section 5.1: the PCG stops on the unpreconditioned residual (relative
+    to ||rhs||_2, the reading of the tolerance).  The iterates x_j are taken
+    from runs capped at j iterations, and their residuals are recomputed here
+    from K: the returned count k must be the first j whose true residual is
+    at or below tol.  The system is scaled so that a stop on ||z|| = ||D^-1 r||
+    or on the D^-1-norm of r would stop at a different iteration (asserted),
+    so either mistake fails this pin."""
+    rng = np.random.default_rng(20)
+    prob = general(24, n=30, m=25, me=2, mg=10)
+    st = random_state(prob, rng, 1.5)        # a wide spread of D entries
+    mu = 0.05
+    K = O.spectrum.kkt_dense(prob, st, mu)
+    rhs, _ = O.newton_rhs_doubly(prob, st, mu)
+    dg = np.diag(K)
+    tol = 1e-7
+    x, k, conv, rr = pcg(lambda v: K @ v, rhs, dg, tol, 5000)
+    assert conv and 2 < k < 5000
+    iters = [pcg(lambda v: K @ v, rhs, dg, tol, j)[0] for j in range(k + 1)]
+    assert np.array_equal(iters[k], x)
+    true = [_true_relres(K, rhs, xj) for xj in iters]
+    first = next(j for j, t in enumerate(true) if t <= tol)
+    assert first == k, (first, k)
+    assert rr == pytest.approx(true[k], rel=1e-6)
+    # a solve capped one iteration early returns that iterate, unconverged
+    xm, km, cm, rm = pcg(lambda v: K @ v, rhs, dg, tol, k - 1)
+    assert km == k - 1 and not cm and np.array_equal(xm, iters[k - 1])
+    assert rm == pytest.approx(true[k - 1], rel=1e-6) and rm > tol
+    # the pin discriminates: preconditioned-norm stop rules cross elsewhere
+    zrel = [np.linalg.norm((rhs - K @ xj) / dg) / np.linalg.norm(rhs / dg) for xj in iters]
+    drel = [np.sqrt(((rhs - K @ xj) ** 2 / dg).sum() / (rhs ** 2 / dg).sum()) for xj in iters]
+    assert next((j for j, t in enumerate(zrel) if t <= tol), None) != k
+    assert next((j for j, t in enumerate(drel) if t <= tol), None) != k
+
+
+def test_pcg_starts_at_zero_and_first_step_is_the_jacobi_steepest_descent_step():
+    """x0 = 0 (reading of Section 5.1); with z0 = D^-1 rhs the first iterate is
+    x1 = (rhs^T z0 / z0^T K z0) z0 in closed form, which fixes both the start
+    and the Jacobi preconditioner D = diag(K) of Section 3.1."""
+    rng = np.random.default_rng(14)
+    prob = general(18, n=12, m=9, me=1, mg=5)
+    st = random_state(prob, rng, 1.0)
+    K = O.spectrum.kkt_dense(prob, st, 0.3)
+    rhs, _ = O.newton_rhs_doubly(prob, st, 0.3)
+    dg = np.diag(K)
+    x0, k0, c0, r0 = pcg(lambda v: K @ v, rhs, dg, 1e-7, 0)
+    assert k0 == 0 and not c0 and np.all(x0 == 0) and r0 == pytest.approx(1.0, rel=1e-15)
+    z0 = rhs / dg
+    x1 = (rhs @ z0) / (z0 @ K @ z0) * z0
+    xp, k1, _, _ = pcg(lambda v: K @ v, rhs, dg, 1e-7, 1)
+    assert k1 == 1 and np.allclose(xp, x1, rtol=1e-13, atol=0)
+
+
+# -------------------------------------- adjoint: lower rows and equality rows
+def test_adjoint_equality_only_closed_form():
+    """Only C x = b: at fixed mu the penalty-barrier conditions are linear,
+    (H + C^T C / mu) x = -p + C^T b / mu, so for L(x) with gradient g,
+    dL/dp = -M^-1 g and dL/db = C M^-1 g / mu with M = H + C^T C / mu."""
+    rng = np.random.default_rng(15)
+    n, me = 7, 3
+    G = rng.standard_normal((n, n))
+    H = G.T @ G + np.eye(n)
+    C = rng.standard_normal((me, n))
+    prob = O.from_spec(W.QPSpec(n=n, c=rng.standard_normal(n), h_kind="dense", H=H, C=C,
+                                b=rng.standard_normal(me)))
+    r = O.solve(prob)
+    g = rng.standard_normal(n)
+    out = O.adjoint_gradients(prob, r.state, r.mu, g)
+    M = H + C.T @ C / r.mu
+    v = np.linalg.solve(M, g)
+    # both solves are backward stable: they agree to about cond(M) * eps
+    bound = 100 * np.linalg.cond(M) * np.finfo(float).eps
+    assert rel(out["c"], -v) <= bound
+    assert rel(out["b"], C @ v / r.mu) <= bound
+
+
+def test_adjoint_lower_rows_and_equality_rhs_match_central_differences():
+    """dL/dl_A (rows with a finite lower side, several of them active) and
+    dL/db (equality rows) from the adjoint agree with central differences of
+    the exactly centered solution at fixed mu (h = 1e-6), along seeded random
+    directions and single coordinates.  The closed form above pins dL/db only
+    without inequalities; this pins the sign and scale with them."""
+    import copy
+    rng = np.random.default_rng(16)
+    base = W.random_bounded_qp(1, 8, 7, 2, 4)
+    prob = O.from_spec(base)
+    S = O.index_sets(prob)
+    r = O.solve(prob)
+    mu = r.mu
+    st = O.center(prob, r.state, mu)
+    assert (st.s_lA < 1e-4).sum() >= 2 and prob.me == 2
+    xref = rng.uniform(-1, 1, base.n)
+    L = lambda x: float(np.sum((x - xref) ** 2))
+    out = O.adjoint_gradients(prob, st, mu, 2 * (st.x - xref))
+    assert np.linalg.norm(out["l"]) > 1e-2 and np.linalg.norm(out["b"]) > 1e-2
+    assert np.all(out["l"][~np.isfinite(prob.l)] == 0)
+
+    def solve_at(spec):
+        return O.center(O.from_spec(spec), st, mu).x
+
+    h = 1e-6
+    for name, key, mask in (("lA", "l", np.isfinite(base.lA)), ("b", "b", np.ones(base.me, bool))):
+        grad = out[key]
+        dirs = []
+        for _ in range(3):
+            v = rng.standard_normal(grad.size) * mask
+            dirs.append(v / np.linalg.norm(v))
+        for i in np.flatnonzero(mask)[:4]:
+            e = np.zeros(grad.size)
+            e[i] = 1.0
+            dirs.append(e)
+        for v in dirs:
+            sp_, sm_ = copy.deepcopy(base), copy.deepcopy(base)
+            setattr(sp_, name, getattr(base, name) + h * v)
+            setattr(sm_, name, getattr(base, name) - h * v)
+            fd = (L(solve_at(sp_)) - L(solve_at(sm_))) / (2 * h)
+            assert abs(fd - grad @ v) <= 1e-4 * max(1e-3, abs(fd)), (name, fd, grad @ v)
