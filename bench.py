@@ -10,12 +10,17 @@ barrier update) of the radiation-therapy-shaped QP:
 Synthetic, seeded data (the paper's clinical problems are not available).
 
 Prints one JSON line.  `value` is PCG iterations per second over the timed
-solves (inputs resident in HBM); `roofline` describes the dominant PCG
-kernel, whose dispatches are sampled (one in --profile-every) with HIP event
-pairs bound to the dispatch on the library's stream; `traffic` is read from
-the committed counter summary under profiles/ when it was taken on the same
-kernel sources; `cpu_baseline` times the CPU oracle's matrix-free PCG on the
-same Newton system for a bounded number of iterations.
+solves (inputs resident in HBM).  `roofline` takes one PCG iteration as its
+unit: the algorithmic bytes of an iteration (`iteration_bytes`: the operator
+once per use the PCG data dependencies require, plus the vectors) over the
+kernel time per iteration, which comes from dispatches sampled (one in
+--profile-every) with HIP event pairs bound to the dispatch on the library's
+stream; the dominant kernel's own figures sit beside it.  `traffic` (HBM
+bytes per iteration) is read from the committed counter summary under
+profiles/ when it was taken on the same kernel sources.  `cpu_baseline` times
+the CPU oracle's matrix-free PCG on the same Newton system for a bounded
+number of iterations, next to the oracle's exact (dense Cholesky) solve time
+stored with the golden solution.
 
   python bench.py --summarize-stats rt_kernel_stats.csv --command "..."
   python bench.py --summarize-counters fetch.csv write.csv --bench-json b.json
@@ -101,6 +106,44 @@ def kernel_bytes(spec, ob, lay, cat, prec_bytes):
     if cat == "cg_pupdate":
         return 3 * 8 * N          # z, p in; p out
     return 0
+
+
+def iteration_bytes(spec, precision):
+    """Algorithmic HBM bytes of one PCG iteration: the operator data once per
+    use that the PCG data dependencies require, plus fourteen touches of a
+    float64 N-vector (a well-fused iteration reads p, x, r, z, diag and the
+    lam-part data and writes q, x, r, z, p).
+
+    * H = P^T W P (radiation therapy): P once.  The product is row-local,
+      P^T (W (P v)) = sum_v P_v^T w_v (P_v . v), so one pass over the rows of P
+      (and of A, whose row epilogue is local too) is enough; a second read of
+      P, as in a two-pass design, is counted as overhead, not as algorithmic.
+    * H = H0 + U W U^T (SVM Gram matrix, quasi-Newton): U twice, since
+      U (W (U^T v)) needs all of U^T v before its second pass can start.
+    * dense H: H once.
+    Values take the stored precision's bytes, sparse column indices 4 bytes
+    (2 bytes with bfloat16 values, which pair with 16-bit column offsets),
+    row pointers 4 bytes."""
+    import scipy.sparse as sp
+    vb = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32x64": 4, "bf16x64": 2}[precision]
+    ib = 2 if vb == 2 else 4
+    n, m, me = spec.n, spec.m, spec.me
+    N = n + me + m
+    total = 14 * 8 * N
+    if spec.h_kind == "ptwp":
+        total += spec.P.nnz * (vb + ib) + 4 * (spec.P.shape[0] + 1) + 8 * spec.P.shape[0]
+    elif spec.h_kind == "lowrank":
+        total += 2 * n * spec.U.shape[1] * vb
+    else:
+        total += n * n * vb
+    if spec.A is not None:
+        if sp.issparse(spec.A):
+            total += spec.A.nnz * (vb + ib) + 4 * (m + 1)
+        else:
+            total += m * n * vb
+    if spec.C is not None:
+        total += me * n * 8
+    return int(total)
 
 
 def source_digest():
@@ -268,10 +311,32 @@ def cpu_baseline(spec, iters):
         t0 = time.perf_counter()
         pcg(mv, rhs, dg, tol=1e-300, maxit=iters)
         dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "PCG iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} iterations of the oracle's Jacobi PCG (matrix-free K v in "
-                      f"NumPy/SciPy, float64, single-threaded) on the first Newton system "
-                      f"of the same workload; {dt:.1f} s"}
+    out = {"value": iters / dt, "unit": "PCG iters/s", "cores": 1, "kind": "oracle",
+           "sample": f"{iters} iterations of the oracle's Jacobi PCG (matrix-free K v in "
+                     f"NumPy/SciPy, float64, single-threaded) on the first Newton system "
+                     f"of the same workload; {dt:.1f} s"}
+    exact = stored_exact_solve(spec)
+    if exact:
+        out["exact_oracle_solve"] = exact
+    return out
+
+
+def stored_exact_solve(spec):
+    """Wall time of the oracle's exact IPM solve (a dense Cholesky factor of
+    the Schur complement Q + B^T D^-1 B at every Newton step) of this
+    workload, as measured when tests/golden/make_golden.py stored its
+    solution: a full solve of that size does not fit the bench's time budget,
+    so it is read back with the host it ran on, not re-measured here."""
+    names = {"rt_200000x20000_nnz0.5pct_maxdose10000": "rt_full.json"}
+    path = os.path.join(ROOT, "tests", "golden", names.get(spec.name, ""))
+    if spec.name not in names or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    return {"ipm_iterations": rec["iterations"], "objective": rec["objective"],
+            "timings": [{k: t[k] for k in ("threads", "ipm_seconds", "form_H_seconds", "nproc", "cpu")
+                         if k in t} for t in rec.get("timings", [])],
+            "how": "measured on the host that wrote tests/golden/rt_full.json (not this run)"}
 
 
 def stream_rates(nbytes, reps=20):
@@ -387,7 +452,14 @@ def main():
     with torch.cuda.stream(stream):
         rates = stream_rates(d["bytes"])
     per_iter_us = sum(v["avg_us"] for v in kern.values())
-    traffic = stored_traffic(args.workload, args.precision, dom)
+    wall_us = solve_s / max(1, total_cg) * 1e6
+    # The roofline unit is one PCG iteration (every PCG kernel above, in
+    # order): its algorithmic bytes over the kernel time per iteration.
+    it_bytes = iteration_bytes(spec, args.precision)
+    achieved = it_bytes / (per_iter_us * 1e-6) / 1e9
+    measured = [stored_traffic(args.workload, args.precision, c) for c in kern]
+    traffic = sum(measured) if measured and all(t is not None for t in measured) else None
+    dom_traffic = stored_traffic(args.workload, args.precision, dom)
     result = {
         "metric": METRIC,
         "value": total_cg / solve_s,
@@ -413,18 +485,26 @@ def main():
         "objective": info.objective,
         "mu_final": info.mu_final,
         "qp_create_s": t_create,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": d["GBs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_us": d["avg_us"], "dispatch_avg_us": d["dispatch_avg_us"],
-                     "algorithmic_bytes_per_launch": d["bytes"],
-                     "launches_timed": d["launches_timed"],
-                     "measured_stream": rates, "frac_of_copy": d["GBs"] / rates["copy_GBs"],
-                     "frac_of_read": d["GBs"] / rates["read_GBs"]},
+        "roofline": {"bound": "hbm", "kernel": "pcg_iteration (" + " + ".join(kern) + ")",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_over_algorithmic": traffic / it_bytes if traffic else None,
+                     "algorithmic_bytes_per_iteration": it_bytes,
+                     "kernel_us_per_iteration": per_iter_us, "wall_us_per_iteration": wall_us,
+                     "frac_wall": it_bytes / (wall_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "measured_stream": rates,
+                     "frac_of_copy": achieved / rates["copy_GBs"],
+                     "dominant_kernel": {"name": dom, "dispatch_avg_us": d["dispatch_avg_us"],
+                                         "avg_us": d["avg_us"], "bytes_per_launch": d["bytes"],
+                                         "GBs": d["GBs"], "frac_of_peak": d["GBs"] / HBM_PEAK_GBS,
+                                         "frac_of_copy": d["GBs"] / rates["copy_GBs"],
+                                         "traffic": dom_traffic,
+                                         "launches_timed": d["launches_timed"]}},
         "kernels": kern,
         "layout": lay,
         "copy_calibration_bytes": calib,
         "pcg_kernel_us_per_iteration": per_iter_us,
-        "pcg_wall_us_per_iteration": solve_s / max(1, total_cg) * 1e6,
+        "pcg_wall_us_per_iteration": wall_us,
         # the same count over the time inside the PCG solves only (the IPM's
         # own kernels and host steps excluded); `value` keeps the whole solve
         "pcg_iters_per_s_inside_pcg": total_cg / max(1e-9, sum(i.pcg_time_ms for i in infos) / 1e3),

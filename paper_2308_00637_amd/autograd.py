@@ -1,6 +1,9 @@
 """Differentiable QP layer: a torch.autograd.Function around ipm_solve /
 qp_backward (argument marshalling only; both directions run in libqpk).
 
+One handle holds one solve: backward must run before the next forward on
+the same handle (it raises otherwise); use one QP per concurrent solve.
+
 The forward pass solves the QP for the given linear term c, row bounds lA,
 uA and (for H = P^T W P) voxel weights w; the backward pass differentiates
 the solution x* through the perturbed optimality conditions at the returned
@@ -25,12 +28,19 @@ class QPFunction(torch.autograd.Function):
         if out["info"].result != 0:
             raise RuntimeError("interior point solve did not converge")
         ctx.qp = qp
+        ctx.generation = qp.generation
         ctx.has = (c is not None, lA is not None, uA is not None, w is not None)
         return out["x"]
 
     @staticmethod
     def backward(ctx, grad_x):
         qp = ctx.qp
+        if qp.generation != ctx.generation:
+            # the handle now holds another solve (a later forward, or a call
+            # that changed its data or iterate): its adjoint would belong to that
+            raise RuntimeError("QPFunction.backward: the QP handle was solved or modified "
+                               "after this forward; run backward before the next forward "
+                               "on the same handle, or use one handle per solve")
         want = [k for k, h in zip(("c", "lA", "uA", "w"), ctx.has) if h]
         g, _ = qp.backward(grad_x.contiguous(), want=tuple(want),
                            opts=default_pcg_options(tol=1e-10, maxit=20000))

@@ -825,8 +825,15 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
         cval[pos] = val[q];
       }
   }
-  // work items: per chunk, proportional to its entries, rows cut at equal entry counts
-  const int target = std::max(nchunk, 256 * per_cu - nchunk);
+  // work items: per chunk, proportional to its entries, rows cut at equal entry counts.
+  // A pass writes one partial slot per work item and the PCG kernels sum at
+  // most kGridMax of them: chunk i gets at most 1 + target * (its share of the
+  // entries) items, so target <= kGridMax - nchunk keeps the count in range.
+  if (nchunk > kGridMax / 2) {
+    h->err = "blocked operator: too many column chunks (" + std::to_string(nchunk) + ")";
+    return QP_ERR_UNSUPPORTED;
+  }
+  const int target = std::min(kGridMax - nchunk, std::max(nchunk, 256 * per_cu - nchunk));
   std::vector<int32_t> work;
   for (int c = 0; c < nchunk; ++c) {
     const int items =
@@ -846,6 +853,10 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
       r = r1;
       if (r >= nrows) break;
     }
+  }
+  if ((int64_t)(work.size() / 3) > kGridMax) {
+    h->err = "blocked operator: more work items than partial-sum slots";
+    return QP_ERR_UNSUPPORTED;
   }
   ck.nrows = (int)nrows;
   ck.ncols = ncols;

@@ -258,6 +258,9 @@ class QP:
             raise QPError(st, LIB.qp_last_error(None).decode())
         self.h = h
         self.precision = precision
+        # bumped by every call that changes the handle's data or iterate, so
+        # a saved solve can tell whether the handle still holds it
+        self.generation = 0
         self.p_rows = int(spec.P.shape[0]) if spec.h_kind == "ptwp" else 0
         sz = [C.c_int64() for _ in range(5)]
         LIB.qp_sizes(h, *[C.byref(v) for v in sz])
@@ -285,6 +288,7 @@ class QP:
 
     # iterate I/O
     def set_state(self, x, lam, s, mu):
+        self.generation += 1
         self._check(LIB.qp_set_state(self.h, _dev(x), _dev(lam), _dev(s), float(mu)))
 
     def get_state(self):
@@ -294,6 +298,7 @@ class QP:
         return x, lam, s, mu.value
 
     def init_state(self, mu=1.0):
+        self.generation += 1
         self._check(LIB.qp_init_state(self.h, float(mu)))
 
     # steps a1..a8
@@ -334,6 +339,7 @@ class QP:
         return ax.value, al.value
 
     def take_step(self, dx, dlam, ds, ax, al):
+        self.generation += 1
         self._check(LIB.qp_take_step(self.h, _dev(dx), _dev(dlam), _dev(ds), float(ax), float(al)))
 
     # Algorithm 1
@@ -359,6 +365,7 @@ class QP:
             x, lam, s = self._empty(self.sizes.n), self._empty(self.sizes.lam), self._empty(self.sizes.s)
         else:
             x = lam = s = None
+        self.generation += 1
         self._check(LIB.ipm_solve(self.h, C.byref(opts), _dev(x), _dev(lam), _dev(s), C.byref(info)))
         if logs is not None:
             k = info.iterations
@@ -366,6 +373,7 @@ class QP:
         return dict(x=x, lam=lam, s=s, info=info, log=logs)
 
     def update_data(self, c=None, lA=None, uA=None, b=None, w=None):
+        self.generation += 1
         self._check(LIB.qp_update_data(self.h, _dev(c), _dev(lA), _dev(uA), _dev(b), _dev(w)))
 
     def profile_begin(self, max_launches: int, every: int = 1):

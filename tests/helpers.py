@@ -94,3 +94,43 @@ def dir_to_masked(prob, d):
     st = O.State(d.dx, d.dlam_e, d.dlam_lA, d.dlam_uA, d.dlam_lx, d.dlam_ux,
                  d.ds_lA, d.ds_uA, d.ds_lx, d.ds_ux)
     return to_masked(prob, st)
+
+
+def block_rel(a, b, sizes):
+    """Largest relative error over consecutive blocks of the given sizes, each
+    measured against its own norm (floored at 1e-14 of the whole vector's,
+    so blocks that are rounding noise compare absolutely): an error confined
+    to a block of small magnitude is not hidden by a large one elsewhere."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    assert a.shape == b.shape and sum(sizes) == b.size, (a.shape, b.shape, sizes)
+    floor = max(1e-14 * np.linalg.norm(b), 1e-300)
+    worst, o = 0.0, 0
+    for k in sizes:
+        if k:
+            worst = max(worst, float(np.linalg.norm(a[o:o + k] - b[o:o + k])
+                                     / max(np.linalg.norm(b[o:o + k]), floor)))
+        o += k
+    return worst
+
+
+def kkt_blocks(prob):
+    """Block sizes of a compact doubly augmented vector: x, lam_e, lam_lA, lam_uA."""
+    S = O.index_sets(prob)
+    return [prob.n, prob.me, S.L.size, S.U.size]
+
+
+def res_blocks(prob):
+    """Block sizes of the library's residual stack (masked layout)."""
+    n, m, me = prob.n, prob.m, prob.me
+    return [n, me, m, m, n, n, m, m, n, n]
+
+
+def lam_blocks(prob):
+    n, m, me = prob.n, prob.m, prob.me
+    return [me, m, m, n, n]
+
+
+def s_blocks(prob):
+    n, m = prob.n, prob.m
+    return [m, m, n, n]

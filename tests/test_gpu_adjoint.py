@@ -1,7 +1,10 @@
 """qp_backward (adjoint PCG on the doubly augmented matrix) against the
 oracle's adjoint, which solves the transposed unreduced Jacobian of eq. (7)
 by dense LU at the same point.  The oracle adjoint itself is pinned by central
-differences of centered solves (tests/test_oracle_pins.py)."""
+differences of centered solves (tests/test_oracle_pins.py), for c, lA, uA, b
+and w.  Every gradient output is compared: the radiation-therapy cases have
+upper rows only (dL/dlA must be 0 there), the general QP has lower, upper and
+two-sided rows and equality rows."""
 import numpy as np
 import pytest
 
@@ -29,6 +32,42 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
+def general_case():
+    """Two-sided, lower-only and upper-only rows, three equality rows, mixed
+    variable bounds (dense H = G^T G + 0.01 I)."""
+    return W.random_bounded_qp(31, 40, 36, 3, 12)
+
+
+def test_backward_lower_rows_and_equalities_match_oracle_adjoint():
+    from paper_2308_00637_amd.qpk import QP, default_pcg_options
+    spec = general_case()
+    prob = O.from_spec(spec)
+    S = O.index_sets(prob)
+    assert S.L.size and S.U.size and prob.me == 3
+    xref = np.random.default_rng(7).uniform(-0.5, 0.5, spec.n)
+    qp = QP(spec)
+    out = qp.solve()
+    info = out["info"]
+    assert info.result == 0
+    x = out["x"].cpu().numpy()
+    gx = 2.0 * (x - xref)
+    g, pinfo = qp.backward(dev(gx), opts=default_pcg_options(tol=1e-12, maxit=50000))
+    print(f"general: ipm={info.iterations} adjoint pcg iters={pinfo.iterations} "
+          f"relres={pinfo.rel_residual:.2e}", flush=True)
+    assert pinfo.converged == 1
+    st = from_masked(prob, x, out["lam"].cpu().numpy(), out["s"].cpu().numpy())
+    ref = O.adjoint_gradients(prob, st, info.mu_final, gx)
+    for key, ok in (("c", "c"), ("lA", "l"), ("uA", "u"), ("b", "b")):
+        got, want = g[key].cpu().numpy(), ref[ok]
+        e = rel(got, want)
+        print(f"  d/d{key}: rel err {e:.2e} (norm {np.linalg.norm(want):.3e})", flush=True)
+        assert np.linalg.norm(want) > 1e-3, key   # the case exercises this output
+        assert e <= 1e-6, key
+    # rows without a finite side carry no gradient for it
+    assert np.all(g["lA"].cpu().numpy()[np.setdiff1d(np.arange(prob.m), S.L)] == 0.0)
+    assert np.all(g["uA"].cpu().numpy()[np.setdiff1d(np.arange(prob.m), S.U)] == 0.0)
+
+
 @pytest.mark.parametrize("case", ["small", "rt_20000x2000"])
 def test_backward_matches_oracle_adjoint(case):
     from paper_2308_00637_amd.qpk import QP, default_pcg_options
@@ -52,6 +91,7 @@ def test_backward_matches_oracle_adjoint(case):
         print(f"  d/d{key}: rel err {e:.2e} (norm {np.linalg.norm(ref[ok]):.3e})", flush=True)
         assert e <= 1e-6, key
     assert np.all(g["lA"].cpu().numpy() == 0.0)   # no row has a finite lower side
+    assert g["b"] is None                           # no equality rows
 
 
 def test_backward_before_solve_is_a_state_error():
@@ -85,3 +125,28 @@ def test_autograd_function():
     # a second forward with changed data reuses the handle
     x2 = qp_layer(qp, c=(c.detach() * 1.01))
     assert torch.isfinite(x2).all() and not torch.equal(x2, x.detach())
+
+
+def test_autograd_backward_after_a_later_forward_raises():
+    """One handle holds one solve: the graph of an earlier forward must not
+    differentiate a later solve.  The latest forward's backward still matches
+    the oracle."""
+    from paper_2308_00637_amd.autograd import qp_layer
+    from paper_2308_00637_amd.qpk import QP
+    spec = small_case()
+    prob = O.from_spec(spec)
+    qp = QP(spec)
+    xref = dev(np.random.default_rng(5).uniform(0, 1, spec.n))
+    c1 = dev(spec.c).requires_grad_(True)
+    c2 = dev(spec.c * 1.01).requires_grad_(True)
+    loss1 = ((qp_layer(qp, c=c1) - xref) ** 2).sum()
+    x2 = qp_layer(qp, c=c2)
+    loss2 = ((x2 - xref) ** 2).sum()
+    loss2.backward()
+    x, lam, s, mu = qp.get_state()
+    st = from_masked(prob, x.cpu().numpy(), lam.cpu().numpy(), s.cpu().numpy())
+    # the Jacobian of eq. (7) does not involve c: the problem as built serves
+    ref = O.adjoint_gradients(prob, st, mu, 2 * (st.x - xref.cpu().numpy()))
+    assert rel(c2.grad.cpu().numpy(), ref["c"]) <= 1e-6
+    with pytest.raises(RuntimeError, match="solved or modified"):
+        loss1.backward()

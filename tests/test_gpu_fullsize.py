@@ -1,8 +1,15 @@
 """Parity at the full radiation-therapy size (200,000 voxels x 20,000
 beamlets, 10,000 max-dose rows) in the launch configuration the benchmark
-times.  The dense oracle cannot run here, so the checks use the oracle's
-matrix-free functions (residuals, K v, Jacobi diagonal) and properties that
-hold at any size."""
+times.  The steps are checked with the oracle's matrix-free functions
+(residuals, K v, Jacobi diagonal); the solve against the oracle's exact IPM
+solve of the same problem (dense Cholesky of the Schur complement at every
+Newton step), stored in tests/golden/rt_full.json by
+tests/golden/make_golden.py because it takes tens of minutes; the
+reduced-precision solves by the oracle's residual function and against the
+float64 solve."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -75,3 +82,58 @@ def test_ipm_solve_kkt_by_oracle_function(full):
     # f(x) - f* <= sum(lam * s) + O(||r||)
     gap = float(gst.lam_uA @ gst.s_uA + gst.lam_lx @ gst.s_lx)
     assert gap <= 1e-6 * (prob.n + prob.m) * 10
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rt_full.json")
+
+
+@pytest.fixture(scope="module")
+def solved(full):
+    spec, prob, qp = full
+    out = qp.solve(log=True)
+    return out
+
+
+def test_ipm_solve_matches_oracle_exact_solve(full, solved):
+    """Relative objective error <= 1e-6 against the oracle's exact solve (both
+    stop at mu = 1e-7 with ||r|| < mu), and the solution itself: both points
+    lie within O(mu) of the same central-path point."""
+    spec, prob, qp = full
+    with open(GOLDEN) as fh:
+        ref = json.load(fh)
+    assert ref["status"] == "converged" and ref["generator"] == "workloads.rt_full()"
+    info = solved["info"]
+    x = solved["x"].cpu().numpy()
+    xo = np.array(ref["x"])
+    obj_err = abs(info.objective - ref["objective"]) / abs(ref["objective"])
+    dx = float(np.max(np.abs(x - xo)))
+    print(f"objective gpu={info.objective:.12g} oracle={ref['objective']:.12g} rel={obj_err:.2e}; "
+          f"max|x - x_oracle|={dx:.2e} (max x {xo.max():.3f}); ipm gpu={info.iterations} "
+          f"oracle={ref['iterations']}; mu_final {info.mu_final:.1e}/{ref['mu_final']:.1e}", flush=True)
+    assert obj_err <= 1e-6
+    assert info.mu_final == ref["mu_final"]
+    assert dx <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp32x64", "fp32", "bf16x64", "bf16"])
+def test_reduced_precision_solve_at_full_size(full, solved, prec):
+    """The reduced-precision operator (float32 or bfloat16 values; float64 or
+    float32 accumulation) with float64 reductions, residual replacement and
+    float64 acceptance: KKT residual <= 1e-4 by the oracle's own function,
+    and the error against the float64 solve stated per result."""
+    from paper_2308_00637_amd.qpk import QP
+    spec, prob, _ = full
+    out = QP(spec, precision=prec).solve()
+    info = out["info"]
+    gst = from_masked(prob, out["x"].cpu().numpy(), out["lam"].cpu().numpy(), out["s"].cpu().numpy())
+    kkt = O.stacked_norm(O.residuals(prob, gst, info.mu_final))
+    f64 = solved["info"]
+    x64 = solved["x"].cpu().numpy()
+    obj_err = abs(info.objective - f64.objective) / abs(f64.objective)
+    dx = float(np.max(np.abs(gst.x - x64)))
+    print(f"{prec}: ipm={info.iterations} cg={info.total_cg_iters} escalations={info.cg_escalations} "
+          f"caps={info.cg_maxiter_hits} time={info.time_ms / 1e3:.2f}s kkt={kkt:.2e} "
+          f"obj vs fp64 {obj_err:.2e} max|dx| vs fp64 {dx:.2e}", flush=True)
+    assert info.result == 0
+    assert kkt <= 1e-4
+    assert obj_err <= 1e-6

@@ -36,7 +36,8 @@ def dev(a):
 
 def make_qp(spec, env):
     from paper_2308_00637_amd.qpk import QP
-    keys = ("QPK_KV_R", "QPK_KV_X", "QPK_ALTERNATE", "QPK_FOLD_A")
+    keys = ("QPK_KV_R", "QPK_KV_X", "QPK_ALTERNATE", "QPK_FOLD_A", "QPK_CHUNK_COLS_R",
+            "QPK_CHUNK_COLS_X")
     old = {k: os.environ.get(k) for k in keys}
     try:
         for k in keys:
@@ -193,3 +194,43 @@ def test_twin_rows_with_repeats(kind):
     qp.newton_rhs()
     y = kkt_from_masked(prob, qp.kkt_matvec(dev(kkt_to_masked(prob, v))).cpu().numpy())
     assert rel(y, O.kkt_matvec(prob, st, 1.0, v)) <= 1e-12
+
+
+NARROW = {
+    # single-chunk column side (15 dense rows of A), narrowest chunks: more
+    # than kGridMax work items unless the builder caps them
+    "lowrank_rows_1024": lambda: W.qn_rt(15, 30_000, 4, 15),
+    # several chunks on both sides at the narrowest width
+    "rt_1024": lambda: W.rt_qp(16, 6_001, 3_001, 0.01, 600, name="rt_6001x3001"),
+}
+
+
+@pytest.mark.parametrize("name", list(NARROW))
+def test_narrowest_chunks_stay_within_partial_slots(name):
+    """QPK_CHUNK_COLS_R/_X = 1024 (the narrowest chunk width): the work items
+    of every pass fit the 2048 partial-sum slots, and K v and thirty CG
+    iterations still match the oracle."""
+    from oracle.pcg import pcg
+    from paper_2308_00637_amd.qpk import default_pcg_options
+    spec = NARROW[name]()
+    prob = O.from_spec(spec)
+    qp = make_qp(spec, {"QPK_CHUNK_COLS_R": 1024, "QPK_CHUNK_COLS_X": 1024})
+    lay = qp.operator_layout()
+    print(f"case={name} layout={lay}", flush=True)
+    assert all(lay[side]["work_items"] <= 2048 for side in ("row", "col"))
+    assert any(lay[side]["chunk_cols"] == 1024 for side in ("row", "col"))
+    qp.init_state(1.0)
+    st = O.initial_point(prob)
+    v = np.random.default_rng(3).standard_normal(prob.n + prob.me + len(O.index_sets(prob).L)
+                                                 + len(O.index_sets(prob).U))
+    y = kkt_from_masked(prob, qp.kkt_matvec(dev(kkt_to_masked(prob, v))).cpu().numpy())
+    assert rel(y, O.kkt_matvec(prob, st, 1.0, v)) <= 1e-12
+    rhs, _ = qp.newton_rhs()
+    ref_rhs, _ = O.newton_rhs_doubly(prob, st, 1.0)
+    dg = O.jacobi_diagonal(prob, st, 1.0)
+    x_ref, its, _, _ = pcg(lambda p: O.kkt_matvec(prob, st, 1.0, p), ref_rhs, dg, tol=1e-300, maxit=30)
+    sol, info = qp.kkt_pcg_solve(rhs, default_pcg_options(maxit=30, tol=1e-300))
+    assert its == 30 and info.iterations == 30
+    err = rel(kkt_from_masked(prob, sol.cpu().numpy()), x_ref)
+    print(f"{name}: 30 CG iterates differ by {err:.2e}", flush=True)
+    assert err <= 1e-9

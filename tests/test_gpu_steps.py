@@ -1,13 +1,17 @@
 """GPU parity of every step of the hot path against the CPU oracle, through
-the C ABI (steps a1-a8 at arbitrary interior states, then Algorithm 1)."""
+the C ABI (steps a1-a8 at arbitrary interior states, then Algorithm 1).
+Vectors are compared block by block (each block of the residual stack, the
+doubly augmented vector and the iterate against its own norm), so an error
+confined to a small block is not hidden by a large one."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
 import oracle as O
 from paper_2308_00637_amd import workloads as W
-from tests.helpers import (dir_to_masked, from_masked, kkt_from_masked, kkt_to_masked,
-                           random_state, rel, res_to_masked, to_masked)
+from tests.helpers import (block_rel, dir_to_masked, from_masked, kkt_blocks, kkt_from_masked,
+                           kkt_to_masked, lam_blocks, random_state, rel, res_blocks,
+                           res_to_masked, s_blocks, to_masked)
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +75,7 @@ def test_a1_residuals(setup):
     r, norms = qp.residuals()
     res = O.residuals(prob, st, mu)
     ref = res_to_masked(prob, res)
-    assert rel(host(r), ref) <= 1e-12
+    assert block_rel(host(r), ref, res_blocks(prob)) <= 1e-12
     pr, du, co = O.infeasibilities(res)
     assert norms[0] == pytest.approx(O.stacked_norm(res), rel=1e-12)
     assert norms[1:] == pytest.approx([pr, du, co], rel=1e-12, abs=1e-300)
@@ -82,8 +86,9 @@ def test_a2_a3_rhs_and_jacobi(setup):
     rhs, dg = qp.newton_rhs()
     ref_rhs, _ = O.newton_rhs_doubly(prob, st, mu)
     ref_dg = O.jacobi_diagonal(prob, st, mu)
-    assert rel(kkt_from_masked(prob, host(rhs)), ref_rhs) <= 1e-12
-    assert rel(kkt_from_masked(prob, host(dg)), ref_dg) <= 1e-12
+    kb = kkt_blocks(prob)
+    assert block_rel(kkt_from_masked(prob, host(rhs)), ref_rhs, kb) <= 1e-12
+    assert block_rel(kkt_from_masked(prob, host(dg)), ref_dg, kb) <= 1e-12
 
 
 def test_a4_matvec(setup):
@@ -95,7 +100,7 @@ def test_a4_matvec(setup):
         y = qp.kkt_matvec(dev(kkt_to_masked(prob, v)))
         ref = O.kkt_matvec(prob, st, mu, v)
         yh = host(y)
-        assert rel(kkt_from_masked(prob, yh), ref) <= 1e-12
+        assert block_rel(kkt_from_masked(prob, yh), ref, kkt_blocks(prob)) <= 1e-12
         # rows of absent sides are identity rows on a zero input
         assert np.all(yh[np.abs(kkt_to_masked(prob, np.ones(N))) == 0] == 0)
 
@@ -111,7 +116,7 @@ def test_a5_pcg_matches_cholesky_and_oracle_pcg(setup):
     xd = np.linalg.solve(K, ref_rhs)
     sol, info = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-12, maxit=20000))
     assert info.converged == 1 and info.rel_residual <= 1e-11
-    assert rel(kkt_from_masked(prob, host(sol)), xd) <= 1e-7
+    assert block_rel(kkt_from_masked(prob, host(sol)), xd, kkt_blocks(prob)) <= 1e-7
     # iteration count at the paper's tolerance agrees with a textbook PCG
     sol, info = qp.kkt_pcg_solve(rhs, default_pcg_options(tol=1e-7))
     _, it, conv, _ = pcg(lambda v: K @ v, ref_rhs, np.diag(K), 1e-7, 5000)
@@ -126,8 +131,8 @@ def test_a6_direction(setup):
     d, _, _ = O.newton_direction(prob, st, mu)
     rx, rl, rs = dir_to_masked(prob, d)
     assert rel(host(dx), rx) <= 1e-7
-    assert rel(host(dl), rl) <= 1e-7
-    assert rel(host(ds), rs) <= 1e-7
+    assert block_rel(host(dl), rl, lam_blocks(prob)) <= 1e-7
+    assert block_rel(host(ds), rs, s_blocks(prob)) <= 1e-7
 
 
 def test_a7_a8_step_lengths_and_update(setup):
@@ -142,7 +147,9 @@ def test_a7_a8_step_lengths_and_update(setup):
     x1, l1, s1, _ = qp.get_state()
     st1 = O.take_step(st, d, oax, oal)
     ex, el, es = to_masked(prob, st1)
-    assert rel(host(x1), ex) <= 1e-14 and rel(host(l1), el) <= 1e-14 and rel(host(s1), es) <= 1e-14
+    assert rel(host(x1), ex) <= 1e-14
+    assert block_rel(host(l1), el, lam_blocks(prob)) <= 1e-14
+    assert block_rel(host(s1), es, s_blocks(prob)) <= 1e-14
     # restore the module-scoped state
     qp.set_state(x0, l0, s0, mu)
 
@@ -161,17 +168,90 @@ def test_a9_ipm_solve_matches_oracle(setup):
     kkt = O.stacked_norm(O.residuals(prob, gst, info.mu_final))
     assert kkt <= 1e-6, kkt
     assert kkt == pytest.approx(info.rnorm, rel=1e-9)
-    # PCG stops at a relative residual of 1e-7 (Section 5.1), so the GPU's
-    # Newton steps differ from the exact (Cholesky) ones by that much, and
-    # rounding-order differences from the oracle's own PCG would too.  The
-    # decrease rule ||r|| < mu is a threshold, so such differences can move a
-    # decrease by an iteration and shift the rest of the schedule.  The final
-    # point is pinned above; the schedule is checked loosely here.
     assert info.mu_final < 1e-6 and info.mu_final >= 1e-8
-    if info.cg_maxiter_hits == 0:
-        # (a PCG solve stopped at its cap returns a rounding-dependent iterate)
-        assert abs(info.iterations - ref.iterations) <= max(4, ref.iterations // 4), \
-            (info.iterations, ref.iterations)
     mus = out["log"]["mu"]
     assert mus[0] == 1.0 and np.all(np.diff(mus) <= 0)
     assert set(np.round(np.log10(mus)).astype(int)) == set(range(0, -8, -1))
+
+
+# IPM iterations before the first Newton system at which the oracle's own
+# Jacobi PCG (tolerance 1e-7, 5000 iterations) stops at its cap.  A capped PCG
+# returns an iterate that depends on rounding order (5000 steps of a recurrence
+# that has lost orthogonality), so schedules are compared up to there.
+SCHEDULE_PREFIX = {"tiny_dense": 24, "ragged_ptwp": 17, "max_equalities": 16}
+
+
+def oracle_pcg_direction(record):
+    """Newton directions by the oracle's textbook Jacobi PCG on eq. (9)
+    (Section 3.1; tolerance and cap of Section 5.1), recording iterations."""
+    from oracle.pcg import pcg
+
+    def direction(prob, st, mu, res):
+        rhs, _ = O.newton_rhs_doubly(prob, st, mu)
+        dg = O.jacobi_diagonal(prob, st, mu)
+        sol, k, conv, _ = pcg(lambda v: O.kkt_matvec(prob, st, mu, v), rhs, dg, tol=1e-7, maxit=5000)
+        record.append((k, conv))
+        return O.direction_from_solution(prob, st, res, sol)
+    return direction
+
+
+def test_a9_schedule_matches_oracle_pcg_driven_ipm(setup):
+    """Algorithm 1 with PCG directions on both sides: the GPU solve and the
+    oracle's IPM driven by its own Jacobi PCG take the same iterations, drop mu
+    at the same ones (strict ||r|| < mu, mu / 10), and end at the same point."""
+    from paper_2308_00637_amd.qpk import default_ipm_options
+    name, spec, prob, qp, st, mu = setup
+    its = SCHEDULE_PREFIX.get(name, 200)
+    record = []
+    ref = O.solve(prob, O.IPMOptions(max_iter=its), direction=oracle_pcg_direction(record))
+    assert all(conv for _, conv in record)
+    out = qp.solve(default_ipm_options(max_iter=its), log=True)
+    info, lg = out["info"], out["log"]
+    assert (info.result == 0) == (ref.status == "converged")
+    assert info.iterations == ref.iterations, (info.iterations, ref.iterations)
+    assert info.cg_maxiter_hits == 0
+    assert list(lg["mu"]) == [e["mu"] for e in ref.log]
+    cg_gap = max(abs(int(a) - k) for a, (k, _) in zip(lg["cg_iters"], record))
+    r_gap = max(abs(a - e["rnorm"]) / e["rnorm"] for a, e in zip(lg["rnorm"], ref.log))
+    x = host(out["x"])
+    dxm = float(np.max(np.abs(x - ref.state.x) / np.maximum(1.0, np.abs(ref.state.x))))
+    print(f"{name}: {info.iterations} IPM iterations ({'converged' if info.result == 0 else 'prefix'}), "
+          f"CG counts within {cg_gap}, ||r|| within {r_gap:.1e} rel, max|dx| {dxm:.1e}", flush=True)
+    assert cg_gap <= 2
+    assert r_gap <= 1e-6
+    assert dxm <= 1e-6
+
+
+def test_unconstrained_qp_takes_exactly_eight_iterations():
+    """No rows, no bounds: the first Newton step solves H x = -p (to the PCG
+    tolerance), every later residual is below mu, so mu falls 1 -> 1e-7 by
+    tenths and the solve returns after exactly 8 iterations (the strict test
+    mu < 1e-6 fails at mu = 1.0000000000000002e-06), at x = -H^-1 p."""
+    from paper_2308_00637_amd.qpk import QP
+    rng = np.random.default_rng(8)
+    n = 60
+    G = rng.standard_normal((40, n))
+    H = G.T @ G + np.eye(n)
+    c = rng.standard_normal(n)
+    out = QP(W.QPSpec(n=n, c=c, h_kind="dense", H=H, name="unconstrained")).solve(log=True)
+    info = out["info"]
+    assert info.result == 0 and info.iterations == 8
+    mus = [1.0]
+    for _ in range(7):
+        mus.append(mus[-1] / 10.0)
+    assert list(out["log"]["mu"]) == mus
+    x_star = np.linalg.solve(H, -c)
+    assert rel(host(out["x"]), x_star) <= 1e-10
+
+
+def test_box_only_separable_qp_reaches_the_clipped_minimiser():
+    """Diagonal H with bounds only: x* = clip(-c/h, lx, ux) coordinate-wise;
+    the returned point is within O(mu_final) of it."""
+    from paper_2308_00637_amd.qpk import QP
+    spec = CASES["no_rows_bounds_only"]()
+    h = np.diag(spec.H)
+    x_star = np.clip(-spec.c / h, spec.lx, spec.ux)
+    out = QP(spec).solve()
+    info = out["info"]
+    assert info.result == 0
+    assert np.max(np.abs(host(out["x"]) - x_star)) <= 10 * info.mu_final
