@@ -74,7 +74,18 @@ def workload(name):
             "svm_rbf": W.svm_rbf, "qn_rt": W.qn_rt, "tiny_dense": W.tiny_dense}[name]()
 
 
-def kernel_bytes(spec, ob, lay, cat, prec_bytes):
+def fused_bytes(spec, fz, prec_bytes):
+    """Bytes of one dispatch of the fused single-read pass: each stored entry
+    once (value + uint16 column offset), both halves' row pointers, w and the
+    twin map per row of P, the gathered vector, each row's half dots written
+    once and read once by the partner, the per-range x-parts written, and the
+    lam-part data of the rows of A (six values in, two out)."""
+    p_rows = spec.P.shape[0]
+    return (fz["stored"] * (prec_bytes + 2) + 8 * (p_rows + 1) + 12 * p_rows + 8 * spec.n
+            + 16 * p_rows + 8 * fz["ranges"] * spec.n + 64 * spec.m)
+
+
+def kernel_bytes(spec, ob, lay, cat, prec_bytes, fz=None):
     """Algorithmic HBM bytes of one dispatch of a PCG kernel: every stored
     operator entry once (value + uint16 column offset, one row-pointer array
     per LDS chunk), and each vector the kernel must read or write once.  The
@@ -101,6 +112,8 @@ def kernel_bytes(spec, ob, lay, cat, prec_bytes):
         return sum(sides) / max(1, len(sides))
     if cat == "tsreduce":
         return n * k * prec_bytes + 8 * n * (1 + me)
+    if cat == "fused":
+        return fused_bytes(spec, fz, prec_bytes)
     if cat == "cg_update":     # x, p, r, q, diag in; x, r, z out (fused: q_x from partials, diag(H) in)
         return 8 * 8 * N + (8 * n * me + 8 * n if col_fused else 0)
     if cat == "cg_pupdate":
@@ -218,6 +231,8 @@ def kernel_category(lay):
             return "tsreduce"
         if name in ("k_cg_update", "k_cg_pupdate"):
             return name.replace("k_", "")
+        if name.startswith("k_fused<"):
+            return "fused"
         return None
 
     return category
@@ -421,6 +436,7 @@ def main():
         prof = qp.profile_end()
         ob = qp.operator_bytes()
         lay = qp.operator_layout()
+        fz = qp.fused_layout()
         calib = 0
         if args.copy_calib_mb > 0:
             calib = args.copy_calib_mb * (1 << 20)
@@ -444,7 +460,7 @@ def main():
             # time (mean x dispatches) is spread over the real iterations
             avg_s = ms / cnt / 1e3
             per_it = avg_s * seen / total_cg
-            by = kernel_bytes(spec, ob, lay, cat, prec_bytes)
+            by = kernel_bytes(spec, ob, lay, cat, prec_bytes, fz)
             kern[cat] = {"launches_timed": cnt, "dispatches": seen, "dispatch_avg_us": avg_s * 1e6,
                          "avg_us": per_it * 1e6, "bytes": by, "GBs": by / per_it / 1e9}
     dom = max(kern, key=lambda c: kern[c]["avg_us"])
@@ -502,6 +518,7 @@ def main():
                                          "launches_timed": d["launches_timed"]}},
         "kernels": kern,
         "layout": lay,
+        "fused": fz,
         "copy_calibration_bytes": calib,
         "pcg_kernel_us_per_iteration": per_iter_us,
         "pcg_wall_us_per_iteration": wall_us,

@@ -345,7 +345,8 @@ enum {
   QP_PROF_EPILOGUE = 3,   /* sum of per-chunk partials, either side (multi-chunk only) */
   QP_PROF_CGUPDATE = 4,   /* PCG: alpha, x, r, z, r.z */
   QP_PROF_CGPUPDATE = 5,  /* PCG: beta, p */
-  QP_PROF_COUNT = 6
+  QP_PROF_FUSED = 6,      /* fused single-read operator kernel of K v (see qp_fused_layout) */
+  QP_PROF_COUNT = 7
 };
 qp_status qp_profile_begin(qp_handle h, int32_t max_launches, int32_t every);
 qp_status qp_profile_end(qp_handle h, int64_t* launches, double* total_ms, int64_t* dispatches);
@@ -363,6 +364,26 @@ qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
  * writes per-chunk partials that a second kernel adds up. */
 qp_status qp_operator_layout(qp_handle h, int32_t* chunks, int32_t* work_items,
                              int32_t* chunk_cols);
+
+/* The fused single-read product of K v for H = P^T W P (matrix-free as in
+ * Section 3.2; a layout choice of this library, not of the paper).  Every
+ * contribution of a row of P (or of A) to K v depends only on that row's
+ * own dot, so one pass over the rows, each entry read once, forms the whole
+ * product.  Its columns are cut in two halves, each row range is handled by
+ * a pair of blocks that exchange the half dots of their rows through device
+ * memory; sums of the scatter are taken in a run-dependent order, so results
+ * agree with the two-pass kernels to rounding, not bitwise.  qp_create builds
+ * it when H = P^T W P, n <= 20,208 and the operator has at least 2^22
+ * entries (QPK_FUSED=0: never; QPK_FUSED=1: whenever the shape allows);
+ * then every product of the handle uses it.  A pair whose partner never runs
+ * alongside (its wait is bounded by QPK_FUSED_SPIN polls, default 2^21)
+ * invalidates the product; the library then switches the handle to the
+ * two-pass kernels and redoes that product or PCG solve, and reports it here.
+ * HOST outs, any may be NULL: active (1 while products use it), row ranges
+ * (block pairs), columns in the first half, stored entries (with the
+ * even-length padding), and failed (1 after such a switch). */
+qp_status qp_fused_layout(qp_handle h, int32_t* active, int32_t* ranges, int32_t* half_cols,
+                          int64_t* stored, int32_t* failed);
 
 #ifdef __cplusplus
 }

@@ -85,6 +85,23 @@ struct qp_handle_s {
   // twin[v] = the A row that repeats P row v, or -1
   bool fold_a = false;
   int32_t* twin = nullptr;
+  // Fused single-read PCG product (H = P^T W P): the rows of the blocked row
+  // side cut into two column halves, row ranges for block pairs
+  struct Fused {
+    bool on = false;
+    bool failed = false;   // a pair's wait timed out once: two-pass from then on
+    int nrows = 0, half = 0, nrange = 0;
+    int32_t* range = nullptr;
+    int32_t* rowptr = nullptr;
+    uint16_t* col = nullptr;
+    double* val = nullptr;
+    void* val_lo = nullptr;
+    int64_t stored = 0;
+    double* xch = nullptr;
+    double* ypart = nullptr;
+    unsigned long long epoch = 0;
+    int spin_max = 1 << 21;
+  } fz;
   double* coef = nullptr;  // CG alpha/beta record (spectrum estimates), 2 * coef_cap
   int coef_cap = 0;
   std::vector<void*> allocs;
@@ -322,8 +339,12 @@ static bool pcg_fuses_epilogue(qp_handle h) {
   return h->ck_x.on && h->ck_x.nchunk > 1 && h->ck_r.on && h->ck_r.nchunk == 1 && h->nRP > 0;
 }
 
+static bool fused_active(qp_handle h) { return h->fz.on && !h->fz.failed; }
+
 // Step a4: y = K v (v, y: K-vectors).  lo selects the reduced-precision
-// operator copies.  done/bump: PCG early exit and iteration counter.  fuse
+// operator copies.  With the fused layout active, one pass over the rows forms
+// the lam-part and per-range x-parts (k_fused); a PCG iteration's update sums
+// the x-parts itself, other products through the column epilogue.  done/bump: PCG early exit and iteration counter.  fuse
 // (PCG iterations only, when pcg_fuses_epilogue): the x-part of y is left as
 // per-chunk partials, and the row pass's partials carry all of p.q.
 static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, const int* done,
@@ -345,6 +366,36 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     f.we = h->we_mv; f.vl = v + h->n; f.yl = y + h->n;
     f.partout = h->part + P_DOT_TS * kGridMax; f.done = done;
     HIPCHK(launch_ts_finish(TS_MATVEC, f, h->st));
+  }
+  if (fused_active(h)) {
+    RowArgs a = row_args(h, lo);
+    a.r0 = 0; a.r1 = h->fz.nrows; a.v = v;
+    a.vl = h->m > 0 ? v + h->n : v;
+    a.dl = h->dl; a.yl = y + h->n;
+    a.wA = h->wA_mv; a.part0 = h->part + P_DOT_R * kGridMax; a.done = done; a.bump = bump;
+    if (h->fold_a) a.twin = h->twin;
+    a.xdot = fuse ? 1 : 0;
+    a.qdiag = h->qdiag;
+    a.Cm = h->Cm;
+    a.we = h->we_mv;
+    FusedArgs f{};
+    f.nrows = h->fz.nrows; f.ncols = h->n; f.half = h->fz.half; f.nrange = h->fz.nrange;
+    f.range = h->fz.range; f.rowptr = h->fz.rowptr; f.col = h->fz.col;
+    f.val = lo ? h->fz.val_lo : (const void*)h->fz.val;
+    f.nstored = (int32_t)h->fz.stored;
+    f.src = v; f.xch = h->fz.xch; f.abort = h->fl + F_FUSEFAIL;
+    f.epoch = ++h->fz.epoch; f.spin_max = h->fz.spin_max; f.ypart = h->fz.ypart;
+    const KEvents ev = prof_slot(h, QP_PROF_FUSED, prof);
+    HIPCHK(launch_fused(vk, f, a, h->st, &ev));
+    if (!fuse) {
+      ChunkArgs ca{};
+      ca.nrows = h->n; ca.ncols = h->n; ca.nchunk = h->fz.nrange; ca.partial = h->fz.ypart;
+      ColArgs c = col_args(h, lo);
+      c.we = h->we_mv; c.v = v; c.y = y;
+      c.part0 = h->part + P_DOT_X * kGridMax; c.done = done;
+      HIPCHK(launch_chunk_epilogue_col(ca, c, h->g_epi_x, h->st));
+    }
+    return QP_OK;
   }
   if (h->nRP > 0) {
     RowArgs a = row_args(h, lo);
@@ -474,11 +525,13 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
     a.jdiag = h->ones;
   }
   HIPCHK(launch_cg_init(a, h->st));
-  const bool fuse = pcg_fuses_epilogue(h);
-  CgArgs au = a;   // k_cg_update's view: q's x-part from the column partials
+  const bool fused = fused_active(h);
+  const bool fuse = fused || pcg_fuses_epilogue(h);
+  CgArgs au = a;   // k_cg_update's view: q's x-part from the column or range partials
   if (fuse) {
-    au.qpart = h->ck_x.partial;
-    au.nchunk = h->ck_x.nchunk;
+    au.qpart = fused ? h->fz.ypart : h->ck_x.partial;
+    au.nchunk = fused ? h->fz.nrange : h->ck_x.nchunk;
+    if (fused) au.g_r = 2 * h->fz.nrange;
     au.g_x = 0;   // p.q is all in the row pass's partials
     au.me = h->me;
     au.qdiag = h->qdiag;
@@ -552,6 +605,13 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
   // true residual with the float64 operator
   CHK(true_residual(h, rhs, sol));
   CHK(read_back(h));
+  if (fused && h->hfl[F_FUSEFAIL]) {
+    // a block pair of the fused product timed out waiting for its partner
+    // (it never ran alongside): the products since are invalid.  Redo the
+    // solve with the two-pass kernels, which need no partner.
+    h->fz.failed = true;
+    return run_pcg(h, rhs, sol, o, info, force64);
+  }
   const int status = h->hfl[F_STATUS];
   pcg_info inf{};
   inf.iterations = h->hfl[F_ITERS];
@@ -772,59 +832,83 @@ static bool match_twins(int64_t p_rows, const std::vector<int64_t>& prp, const i
   return true;
 }
 
-static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
-                               const std::vector<int32_t>& col, const std::vector<double>& val,
-                               int ncols, int cw_default, int kv_default, bool row_side,
-                               const char* env, const char* env_lpr, const char* env_kv) {
+// Chunk-major storage of a CSR operator whose columns are cut into chunks of
+// cw: chunk c holds its own CSR (row pointers c * (nrows + 1) ...) with uint16
+// column offsets within the chunk; every (chunk, row) segment is padded with
+// zero entries to even length, so kernels load entries in aligned pairs.
+struct ChunkStore {
+  int nchunk = 0;
+  int64_t stored = 0;
+  std::vector<int32_t> rowptr;
+  std::vector<int64_t> nnz;      // entries per chunk, with the padding
+  std::vector<uint16_t> col;
+  std::vector<double> val;
+};
+
+static qp_status chunk_store(qp_handle h, const std::vector<int32_t>& rp, const std::vector<int32_t>& col,
+                             const std::vector<double>& val, int ncols, int cw, ChunkStore& out) {
   const int64_t nrows = (int64_t)rp.size() - 1;
-  // Chunk width (columns staged in LDS per block); `env` overrides it.  A
-  // work item holds at least one (chunk, row) segment, so few long rows (a
-  // handful of dense rows over many columns) get narrower chunks until there
-  // are segments for two blocks per CU.
-  int cw = cw_default;
-  while (cw > 1024 && nrows * ((ncols + cw - 1) / cw) < 512) cw = std::max(1024, cw / 2) & ~1;
-  if (const char* e = std::getenv(env)) {
-    const int v = std::atoi(e);
-    if (v >= 1024 && v <= kChunkCols) cw = v & ~1;
-  }
-  const int per_cu = std::max(1, (int)(163840 / (8 * (int64_t)cw + 1024)));
   const int nchunk = (int)std::max<int64_t>(1, (ncols + cw - 1) / cw);
-  const int64_t nnz = rp[nrows];
   std::vector<int64_t> cnt((size_t)nchunk * nrows, 0);
   for (int64_t r = 0; r < nrows; ++r)
     for (int64_t q = rp[r]; q < rp[r + 1]; ++q) cnt[(size_t)(col[q] / cw) * nrows + r]++;
-  // each (chunk, row) segment is padded with zero entries to even length, so
-  // the kernel loads entries in aligned pairs
-  std::vector<int32_t> crp((size_t)nchunk * (nrows + 1));
-  std::vector<int64_t> cnnz(nchunk, 0);
+  std::vector<int32_t>& crp = out.rowptr;
+  crp.assign((size_t)nchunk * (nrows + 1), 0);
+  out.nnz.assign(nchunk, 0);
   int64_t off = 0;
   for (int c = 0; c < nchunk; ++c) {
     for (int64_t r = 0; r < nrows; ++r) {
       crp[(size_t)c * (nrows + 1) + r] = (int32_t)off;
       off += (cnt[(size_t)c * nrows + r] + 1) & ~int64_t(1);
-      if (off * 8 >= (int64_t(1) << 31)) {   // byte offsets of the kernel's buffer loads
+      if (off * 8 >= (int64_t(1) << 31)) {   // byte offsets of the kernels' buffer loads
         h->err = "blocked operator exceeds 2^28 stored entries";
         return QP_ERR_UNSUPPORTED;
       }
     }
     crp[(size_t)c * (nrows + 1) + nrows] = (int32_t)off;
-    cnnz[c] = crp[(size_t)c * (nrows + 1) + nrows] - crp[(size_t)c * (nrows + 1)];
+    out.nnz[c] = crp[(size_t)c * (nrows + 1) + nrows] - crp[(size_t)c * (nrows + 1)];
   }
-  const int64_t stored = off;
-  std::vector<uint16_t> ccol(stored, 0);
-  std::vector<double> cval(stored, 0.0);
-  {
-    std::vector<int64_t> cur(cnt.size());
-    for (int c = 0; c < nchunk; ++c)
-      for (int64_t r = 0; r < nrows; ++r) cur[(size_t)c * nrows + r] = crp[(size_t)c * (nrows + 1) + r];
-    for (int64_t r = 0; r < nrows; ++r)
-      for (int64_t q = rp[r]; q < rp[r + 1]; ++q) {
-        const int c = col[q] / cw;
-        const int64_t pos = cur[(size_t)c * nrows + r]++;
-        ccol[pos] = (uint16_t)(col[q] - c * cw);
-        cval[pos] = val[q];
-      }
+  out.nchunk = nchunk;
+  out.stored = off;
+  out.col.assign(off, 0);
+  out.val.assign(off, 0.0);
+  std::vector<int64_t> cur(cnt.size());
+  for (int c = 0; c < nchunk; ++c)
+    for (int64_t r = 0; r < nrows; ++r) cur[(size_t)c * nrows + r] = crp[(size_t)c * (nrows + 1) + r];
+  for (int64_t r = 0; r < nrows; ++r)
+    for (int64_t q = rp[r]; q < rp[r + 1]; ++q) {
+      const int c = col[q] / cw;
+      const int64_t pos = cur[(size_t)c * nrows + r]++;
+      out.col[pos] = (uint16_t)(col[q] - c * cw);
+      out.val[pos] = val[q];
+    }
+  return QP_OK;
+}
+
+static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std::vector<int32_t>& rp,
+                               const std::vector<int32_t>& col, const std::vector<double>& val,
+                               int ncols, int cw_default, int kv_default, bool row_side,
+                               const char* env, const char* env_lpr, const char* env_kv) {
+  const int64_t rows_in = (int64_t)rp.size() - 1;
+  // Chunk width (columns staged in LDS per block); `env` overrides it.  A
+  // work item holds at least one (chunk, row) segment, so few long rows (a
+  // handful of dense rows over many columns) get narrower chunks until there
+  // are segments for two blocks per CU.
+  int cw = cw_default;
+  while (cw > 1024 && rows_in * ((ncols + cw - 1) / cw) < 512) cw = std::max(1024, cw / 2) & ~1;
+  if (const char* e = std::getenv(env)) {
+    const int v = std::atoi(e);
+    if (v >= 1024 && v <= kChunkCols) cw = v & ~1;
   }
+  const int per_cu = std::max(1, (int)(163840 / (8 * (int64_t)cw + 1024)));
+  const int64_t nrows = (int64_t)rp.size() - 1;
+  const int64_t nnz = rp[nrows];
+  ChunkStore cs;
+  CHK(chunk_store(h, rp, col, val, ncols, cw, cs));
+  const int nchunk = cs.nchunk;
+  const int64_t stored = cs.stored;
+  const std::vector<int32_t>& crp = cs.rowptr;
+  const std::vector<int64_t>& cnnz = cs.nnz;
   // work items: per chunk, proportional to its entries, rows cut at equal entry counts.
   // A pass writes one partial slot per work item and the PCG kernels sum at
   // most kGridMax of them: chunk i gets at most 1 + target * (its share of the
@@ -885,12 +969,73 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
   if (const char* e = std::getenv("QPK_XCD_MAP")) ck.xcd_map = std::atoi(e) != 0;
   CHK(upload(h, &ck.work, work.data(), (int64_t)work.size()));
   CHK(upload(h, &ck.rowptr, crp.data(), (int64_t)crp.size()));
-  CHK(upload(h, &ck.col, ccol.data(), stored));
-  CHK(upload(h, &ck.val, cval.data(), stored));
-  if (h->vk != VK_F64) CHK(upload_lo(h, &ck.val_lo, cval));
+  CHK(upload(h, &ck.col, cs.col.data(), stored));
+  CHK(upload(h, &ck.val, cs.val.data(), stored));
+  if (h->vk != VK_F64) CHK(upload_lo(h, &ck.val_lo, cs.val));
   if (nchunk > 1) CHK(dalloc_t(h, &ck.partial, (int64_t)nchunk * nrows));
   HIPCHK(hipStreamSynchronize(h->st));  // host staging vectors go out of scope
   ck.on = true;
+  return QP_OK;
+}
+
+// The fused single-read product's layout: the rows of the blocked row side
+// (rows of P, then those of A unless they are folded into P's twins) with
+// their columns cut in two halves of at most kFusedHalfMax, and row ranges of
+// equal entry counts, one per pair of blocks (one block per CU).  Used for
+// H = P^T W P when n <= 2 kFusedHalfMax and the operator is large enough for
+// the pass to stream (QPK_FUSED=0 never, =1 whenever the shape allows).
+static qp_status build_fused(qp_handle h, const std::vector<int32_t>& rp, const std::vector<int32_t>& col,
+                             const std::vector<double>& val, int ncols) {
+  const int64_t nrows = (int64_t)rp.size() - 1;
+  const char* e = std::getenv("QPK_FUSED");
+  const int mode = e ? std::atoi(e) : -1;
+  if (mode == 0 || h->h_kind != QP_H_PTWP || ncols > 2 * kFusedHalfMax || nrows < 1) return QP_OK;
+  if (mode < 0 && rp[nrows] < (int64_t(1) << 22)) return QP_OK;
+  int dev = 0, cus = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int nrange = (int)std::max<int64_t>(1, std::min<int64_t>(cus / 2, nrows));
+  if (2 * nrange > kGridMax) return QP_OK;
+  const int half = (((ncols + 1) / 2) + 1) & ~1;   // even, >= ncols - half
+  ChunkStore cs;
+  CHK(chunk_store(h, rp, col, val, ncols, half, cs));
+  if (cs.nchunk > 2) return QP_OK;
+  if (cs.nchunk == 1) {   // ncols <= half: an empty second half
+    cs.rowptr.resize(2 * (size_t)(nrows + 1), (int32_t)cs.stored);
+    cs.nnz.push_back(0);
+  }
+  // row ranges of equal stored entries over both halves
+  std::vector<int32_t> range(nrange + 1, (int32_t)nrows);
+  range[0] = 0;
+  {
+    const int32_t* r0 = cs.rowptr.data();
+    const int32_t* r1 = cs.rowptr.data() + (nrows + 1);
+    const int64_t total = cs.stored;
+    int64_t acc = 0;
+    int next = 1;
+    for (int64_t r = 0; r < nrows && next < nrange; ++r) {
+      acc += (r0[r + 1] - r0[r]) + (r1[r + 1] - r1[r]);
+      while (next < nrange && acc * nrange >= total * next) range[next++] = (int32_t)(r + 1);
+    }
+  }
+  qp_handle_s::Fused& fz = h->fz;
+  fz.nrows = (int)nrows;
+  fz.half = half;
+  fz.nrange = nrange;
+  fz.stored = cs.stored;
+  CHK(upload(h, &fz.range, range.data(), (int64_t)range.size()));
+  CHK(upload(h, &fz.rowptr, cs.rowptr.data(), (int64_t)cs.rowptr.size()));
+  CHK(upload(h, &fz.col, cs.col.data(), cs.stored));
+  CHK(upload(h, &fz.val, cs.val.data(), cs.stored));
+  if (h->vk != VK_F64) CHK(upload_lo(h, &fz.val_lo, cs.val));
+  CHK(dalloc_t(h, &fz.xch, 4 * nrows));
+  // every exchange slot starts empty (all bits set)
+  HIPCHK(hipMemsetAsync(fz.xch, 0xff, sizeof(double) * 4 * nrows, h->st));
+  CHK(dalloc_t(h, &fz.ypart, (int64_t)nrange * ncols));
+  if (const char* sm = std::getenv("QPK_FUSED_SPIN")) fz.spin_max = std::max(1, std::atoi(sm));
+  HIPCHK(fused_set_attributes());
+  HIPCHK(hipStreamSynchronize(h->st));  // host staging vectors go out of scope
+  fz.on = true;
   return QP_OK;
 }
 
@@ -1127,10 +1272,12 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
     CHK(build_chunked(h, h->ck_x, xrp_p, scol_p, xval_p, (int)p_rows, kChunkCols / 2, 1, false,
                       "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
     CHK(upload(h, &h->twin, twin.data(), (int64_t)twin.size()));
+    CHK(build_fused(h, rrp_p, rcol, rval, (int)n));
   } else {
     if (h->nRP > 0)
       CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, true, "QPK_CHUNK_COLS_R",
                         "QPK_LPR_R", "QPK_KV_R"));
+    if (h->nRP > 0 && want_ck_x) CHK(build_fused(h, rrp, rcol, rval, (int)n));
     if (want_ck_x)
       CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1, false,
                         "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
@@ -1358,7 +1505,15 @@ qp_status qp_newton_rhs(qp_handle h, double* rhs, double* jacobi_diag) {
 qp_status qp_kkt_matvec(qp_handle h, const double* v, double* y) {
   if (!h || !v || !y) return QP_ERR_ARG;
   CHK(prepare(h));
+  const bool fused = fused_active(h);
   CHK(run_matvec(h, false, v, y, nullptr, nullptr));
+  if (fused) {
+    CHK(read_back(h));
+    if (h->hfl[F_FUSEFAIL]) {   // a block pair timed out: redo it with the two-pass kernels
+      h->fz.failed = true;
+      CHK(run_matvec(h, false, v, y, nullptr, nullptr));
+    }
+  }
   HIPCHK(hipStreamSynchronize(h->st));
   return QP_OK;
 }
@@ -1631,6 +1786,17 @@ qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
   if (dense_bytes) *dense_bytes = (int64_t)h->n * h->k * vb;
   if (row_nnz) *row_nnz = h->nnz_rp;
   if (col_nnz) *col_nnz = h->nnz_xs;
+  return QP_OK;
+}
+
+qp_status qp_fused_layout(qp_handle h, int32_t* active, int32_t* ranges, int32_t* half_cols,
+                          int64_t* stored, int32_t* failed) {
+  if (!h) return QP_ERR_ARG;
+  if (active) *active = fused_active(h) ? 1 : 0;
+  if (ranges) *ranges = h->fz.on ? h->fz.nrange : 0;
+  if (half_cols) *half_cols = h->fz.on ? h->fz.half : 0;
+  if (stored) *stored = h->fz.on ? h->fz.stored : 0;
+  if (failed) *failed = h->fz.failed ? 1 : 0;
   return QP_OK;
 }
 

@@ -193,6 +193,32 @@ hipError_t launch_chunk_epilogue_row(const ChunkArgs& c, const RowArgs& ra, int 
                                      const KEvents* ev = nullptr);
 hipError_t chunked_set_attributes();
 
+// Fused single-read PCG product for H = P^T W P (see k_fused).  The row
+// operator's columns are cut into two halves (half 0: [0, half), half 1:
+// [half, ncols)); a pair of blocks per row range, one per half, exchanges the
+// half dots of each row through xch.
+constexpr int kFusedLpr = 8;                          // lanes per row
+constexpr int kFusedHalfMax = (163840 - 256) / 16;    // columns per half (LDS: v's and y's half)
+struct FusedArgs {
+  int32_t nrows, ncols;      // rows of the row operator, n
+  int32_t half;              // columns of half 0 (even, >= ncols - half)
+  int32_t nrange;            // row ranges (2 nrange blocks)
+  const int32_t* range;      // nrange + 1 row boundaries
+  const int32_t* rowptr;     // 2 * (nrows + 1): half 0's CSR, then half 1's
+  const uint16_t* col;       // column offsets within the half
+  const void* val;
+  int32_t nstored;
+  const double* src;         // gathered x-space vector (ncols)
+  double* xch;               // 2 parities x 2 halves x nrows half dots (all bits set = empty)
+  int* abort;                // sticky: a wait timed out, the product is invalid
+  unsigned long long epoch;  // launch count (its parity picks the exchange slots)
+  int32_t spin_max;          // bound on a wait's polls
+  double* ypart;             // nrange * ncols: each range's x-part of K v
+};
+hipError_t launch_fused(int vk, const FusedArgs& f, const RowArgs& ra, hipStream_t st,
+                        const KEvents* ev = nullptr);
+hipError_t fused_set_attributes();
+
 }  // namespace qpk
 
 namespace qpk {
@@ -209,7 +235,7 @@ enum Scalar : int {
   S_ALPHA_X = 0, S_ALPHA_L, S_NORM, S_PRIMAL, S_DUAL, S_COMPL, S_RHSNORM,
   S_OBJ, S_RELRES, S_RECUR, S_COUNT
 };
-enum Flag : int { F_DONE = 0, F_CNT, F_STATUS, F_ITERS, F_BAD, F_COUNT };
+enum Flag : int { F_DONE = 0, F_CNT, F_STATUS, F_ITERS, F_BAD, F_FUSEFAIL, F_COUNT };
 
 // Single-block finisher of the tall-skinny reduction.
 enum TsMode : int { TS_MATVEC = 0, TS_RESID = 1, TS_GONLY = 2 };

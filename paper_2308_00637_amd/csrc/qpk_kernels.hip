@@ -817,6 +817,279 @@ __global__ __launch_bounds__(kBlock) void k_chunk_epilogue_row(ChunkArgs b, RowA
   if (threadIdx.x == 0) a.part0[blockIdx.x] = acc0;
 }
 
+// ------------------------------------------ fused single-read PCG product
+// For H = P^T W P every row of the row operator (rows of P, then rows of A,
+// or P alone with its twin map) contributes RP_r^T s_r to the x-part of K v,
+// with s_r = w_r (P_r . v) (+ the weight of the A row it repeats) or, for a
+// row of A, s_r = w_l - w_u: a function of the row's own dot (the matrix-free
+// product of Section 3.2 is row-local).  So one pass over the rows forms the
+// whole x-part, each stored entry read from HBM once and used twice: for the
+// dot and, still in registers, for the scatter.
+//
+// One CU's LDS cannot hold both the gathered vector and the scatter target
+// (2n float64 values at n = 20,000), so the columns are cut in two halves and
+// each row range goes to a pair of blocks, block 2r + h owning half h: it
+// keeps v's half and y's half in LDS, forms the half-h part of each row's dot
+// and exchanges it with its partner through memory.  Both then hold the whole
+// dot (added in the same order) and scatter their half of the row's entries
+// into LDS with float64 atomics.  Each range's y is written to ypart (nrange
+// x n) and the PCG update sums the ranges in order; the atomics' order
+// varies, so products agree with the two-pass kernels to rounding, not
+// bitwise.
+//
+// The exchange is per wave and needs no flag: wave w of either block takes
+// the same rows (8 per tile, one per group of 8 lanes), stores each half dot
+// in its slot of xch with a device-coherent store, and reads the partner's
+// slot with a device-coherent load, which returns the sentinel (all bits
+// set) until the partner's store has landed; the reader then puts the
+// sentinel back.  Slots alternate with the launch parity, so a slot is
+// rewritten only two launches later, after the reset.  Every wave pipelines
+// its own tiles: in phase ph it scatters tile ph-2, issues the partner load
+// of tile ph-1, the row bounds of tile ph+2 and the entries of tile ph+1,
+// then forms tile ph's dots.  Loads are issued in the order they are waited
+// for (the vector memory counter drains in issue order), so no wait holds a
+// tile that is still in flight.  A wait for the partner is bounded: after
+// f.spin_max polls the block sets the sticky abort flag and goes on; the
+// product is then invalid and the host redoes the work with the two-pass
+// kernels.
+
+// Row data of the epilogue, loaded ahead by role: in a tile's load phase
+// lane 0 of the row's group fetches w_r (0 for a row of A) and lane 1 the
+// index i_r of the row of A the row carries (its twin for a row of P, or
+// itself; -1 for none); after the tile's dot lanes 2..7 fetch that row of
+// A's lA, uA, v_lo, v_up, d_lo, d_up.
+__device__ __forceinline__ double fused_field(const RowArgs& a, int role, int i) {
+  switch (role) {
+    case 2: return a.lA[i];
+    case 3: return a.uA[i];
+    case 4: return a.vl[a.me + i];
+    case 5: return a.vl[a.me + a.m + i];
+    case 6: return a.dl[a.me + i];
+    default: return a.dl[a.me + a.m + i];
+  }
+}
+
+constexpr unsigned long long kFusedEmpty = ~0ull;   // an exchange slot not yet written
+
+template <int VK, int PP>
+__global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) {
+  using T = typename VT<VK>::T;
+  using Acc = typename VT<VK>::Acc;
+  constexpr int LPR = kFusedLpr;
+  static_assert(LPR == 8, "the epilogue's row data is spread over eight lanes");
+  constexpr int GW = 64 / LPR;                   // rows per wave tile
+  constexpr int NW = kChunkBlock / 64;           // waves per block
+  constexpr int SPAN = 2 * LPR * PP;             // entries per row per batch
+  if (ra.done && *ra.done) return;
+  if (ra.bump && blockIdx.x == 0 && threadIdx.x == 0) *ra.bump += 1;
+  extern __shared__ __align__(16) double lds[];
+  const int h = static_cast<int>(blockIdx.x & 1), r = static_cast<int>(blockIdx.x >> 1);
+  const int c0 = h ? f.half : 0;
+  const int cw = h ? f.ncols - f.half : f.half;
+  double* vh = lds;                    // v_x[c0, c0 + cw)
+  double* yh = lds + f.half;           // y_x[c0, c0 + cw)
+  const int R0 = f.range[r], R1 = f.range[r + 1];
+  const int wave = static_cast<int>(threadIdx.x) >> 6;
+  const int g = (static_cast<int>(threadIdx.x) & 63) / LPR;   // group in the wave
+  const int lane = threadIdx.x & (LPR - 1);
+  // wave tile k holds rows R0 + (k NW + wave) GW + g
+  const int nt = (R1 - R0 + NW * GW - 1) / (NW * GW);
+  const int32_t* rp = f.rowptr + static_cast<int64_t>(h) * (f.nrows + 1);
+  const T* val = static_cast<const T*>(f.val);
+  const __amdgpu_buffer_rsrc_t rrp = rsrc(rp, 4u * static_cast<uint32_t>(f.nrows + 1));
+  const __amdgpu_buffer_rsrc_t rcol = rsrc(f.col, 2u * static_cast<uint32_t>(f.nstored));
+  const __amdgpu_buffer_rsrc_t rval = rsrc(val, static_cast<uint32_t>(sizeof(T)) * f.nstored);
+  // exchange slots of this launch's parity: [half][row]
+  double* xbase = f.xch + static_cast<int64_t>(f.epoch & 1) * 2 * f.nrows;
+  double* xown = xbase + static_cast<int64_t>(h) * f.nrows;
+  double* xother = xbase + static_cast<int64_t>(h ^ 1) * f.nrows;
+  using LT = decltype(ldv(val, 0));
+
+  for (int i = threadIdx.x; i < cw; i += kChunkBlock) {
+    vh[i] = f.src[c0 + i];
+    yh[i] = 0.0;
+  }
+
+  struct Tile {
+    uint32_t cc[PP];
+    LT vx[PP], vy[PP];
+    int beg, end;
+    double fb;        // this lane's epilogue field (see fused_field)
+    double own;       // lane 0: this half's dot of the group's row
+    double xo;        // lane 0: the partner's half dot, or the sentinel
+  };
+  auto load_batch = [&](int base, int end, uint32_t* cc, LT* vx, LT* vy) {
+#pragma unroll
+    for (int k = 0; k < PP; ++k) {
+      const int q = base + 2 * (lane + k * LPR);
+      const bool ok = q < end;
+      cc[k] = __builtin_amdgcn_raw_buffer_load_b32(rcol, ok ? 2u * q : kOob, 0, 0);
+      ldv2b(val, rval, ok ? static_cast<uint32_t>(sizeof(T)) * q : kOob, vx[k], vy[k]);
+    }
+  };
+  auto row_of = [&](int k) { return R0 + (k * NW + wave) * GW + g; };
+  auto row_ok = [&](int k) { return k >= 0 && k < nt && row_of(k) < R1; };
+  // [rowptr[row], rowptr[row + 1]) of this group's row in tile k, else empty
+  auto bounds = [&](int k, int& beg, int& end) {
+    const i2v be = __builtin_bit_cast(
+        i2v, __builtin_amdgcn_raw_buffer_load_b64(rrp, row_ok(k) ? 4u * row_of(k) : kOob, 0, 0));
+    beg = be.x;
+    end = be.y;
+  };
+  // lanes 0 and 1 fetch w_r and i_r, then every lane the entries of tile k
+  auto load_tile = [&](Tile& tl, int k, int beg, int end) {
+    tl.fb = 0.0;
+    if (row_ok(k)) {
+      const int row = row_of(k);
+      if (lane == 0) tl.fb = row < ra.p_rows ? ra.w[row] : 0.0;
+      if (lane == 1)
+        tl.fb = static_cast<double>(row < ra.p_rows ? (ra.twin ? ra.twin[row] : -1) : row - ra.p_rows);
+    }
+    tl.beg = beg;
+    tl.end = end;
+    load_batch(beg, end, tl.cc, tl.vx, tl.vy);
+  };
+  auto scatter_batch = [&](const uint32_t* cc, const LT* vx, const LT* vy, double s) {
+#pragma unroll
+    for (int k = 0; k < PP; ++k) {
+      // zero entries (the even-length padding, loads past the end) add nothing
+      if (vx[k] != LT(0)) atomicAdd(&yh[cc[k] & 0xffffu], static_cast<double>(vx[k]) * s);
+      if (vy[k] != LT(0)) atomicAdd(&yh[cc[k] >> 16], static_cast<double>(vy[k]) * s);
+    }
+  };
+
+  double acc = 0.0;
+  bool abandoned = __hip_atomic_load(f.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+
+  // Epilogue of this group's row of tile k (lane 0; the row's data spread
+  // over the group's lanes) and the scatter of its entries.
+  auto scatter_tile = [&](Tile& tl, int k) {
+    const bool valid = row_ok(k);
+    double t = 0.0;
+    if (valid && lane == 0) {
+      const int row = row_of(k);
+      unsigned long long bits = __builtin_bit_cast(unsigned long long, tl.xo);
+      for (int spin = 0; bits == kFusedEmpty && !abandoned; ++spin) {
+        // the partner has not stored this row's half dot yet
+        if ((spin & 255) == 255 &&
+            __hip_atomic_load(f.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+          abandoned = true;
+        if (spin >= f.spin_max) {
+          __hip_atomic_store(f.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          abandoned = true;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        bits = __builtin_bit_cast(unsigned long long,
+                                  __hip_atomic_load(xother + row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      }
+      const double o = bits == kFusedEmpty ? 0.0 : __builtin_bit_cast(double, bits);
+      __hip_atomic_store(xother + row, __builtin_bit_cast(double, kFusedEmpty), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      t = h == 0 ? tl.own + o : o + tl.own;     // half 0 first on both sides
+    }
+    const double w = __shfl(tl.fb, 0, LPR);
+    const int i = static_cast<int>(__shfl(tl.fb, 1, LPR));
+    const double lA = __shfl(tl.fb, 2, LPR), uA = __shfl(tl.fb, 3, LPR);
+    const double vlo = __shfl(tl.fb, 4, LPR), vup = __shfl(tl.fb, 5, LPR);
+    const double dlo = __shfl(tl.fb, 6, LPR), dup = __shfl(tl.fb, 7, LPR);
+    t = __shfl(t, 0, LPR);
+    if (!valid) return;
+    const double uv = w * t;
+    double wa = 0.0;
+    if (i >= 0) {
+      const bool hl = has_lo(lA), hu = has_hi(uA);
+      wa = (hl ? 2.0 * t / dlo + vlo : 0.0) - (hu ? -2.0 * t / dup + vup : 0.0);
+      if (h == 0 && lane == 0) {
+        // the lam-part of K v for this row of A, and its terms of p.q
+        const double ylo = (hl ? t : 0.0) + dlo * vlo;
+        const double yup = (hu ? -t : 0.0) + dup * vup;
+        ra.yl[ra.me + i] = ylo;
+        ra.yl[ra.me + ra.m + i] = yup;
+        acc += vlo * ylo + vup * yup + t * wa;
+      }
+    }
+    if (h == 0 && lane == 0) acc += t * uv;
+    const double s = uv + wa;
+    scatter_batch(tl.cc, tl.vx, tl.vy, s);
+    for (int base = tl.beg + SPAN; base < tl.end; base += SPAN) {   // rows past one batch
+      uint32_t c2[PP];
+      LT x2[PP], y2[PP];
+      load_batch(base, tl.end, c2, x2, y2);
+      scatter_batch(c2, x2, y2, s);
+    }
+  };
+
+  int nb = 0, ne = 0;    // bounds of the next tile to load, one phase ahead
+  // one phase: scatter tile ph-2 (tsl), partner load of tile ph-1 (tw), bounds
+  // of tile ph+2, entries of tile ph+1 (into tsl), dots of tile ph (td)
+  auto phase = [&](int ph, Tile& td, Tile& tw, Tile& tsl) {
+    if (ph >= 2) scatter_tile(tsl, ph - 2);
+    tw.xo = 0.0;
+    if (lane == 0 && row_ok(ph - 1))
+      tw.xo = __hip_atomic_load(xother + row_of(ph - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int cb = nb, ce = ne;
+    bounds(ph + 2, nb, ne);
+    load_tile(tsl, ph + 1, cb, ce);
+    if (ph < nt) {
+      Acc t = 0;
+#pragma unroll
+      for (int k = 0; k < PP; ++k) {
+        t += static_cast<Acc>(td.vx[k]) * static_cast<Acc>(vh[td.cc[k] & 0xffffu]);
+        t += static_cast<Acc>(td.vy[k]) * static_cast<Acc>(vh[td.cc[k] >> 16]);
+      }
+      for (int base = td.beg + SPAN; base < td.end; base += SPAN) {
+        uint32_t c2[PP];
+        LT x2[PP], y2[PP];
+        load_batch(base, td.end, c2, x2, y2);
+#pragma unroll
+        for (int k = 0; k < PP; ++k) {
+          t += static_cast<Acc>(x2[k]) * static_cast<Acc>(vh[c2[k] & 0xffffu]);
+          t += static_cast<Acc>(y2[k]) * static_cast<Acc>(vh[c2[k] >> 16]);
+        }
+      }
+      t = group_sum<LPR>(t);
+      td.own = static_cast<double>(t);
+      if (lane == 0 && row_ok(ph))
+        __hip_atomic_store(xown + row_of(ph), td.own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the row of A this row carries: lanes 2..7 fetch its fields
+      const int i = static_cast<int>(__shfl(td.fb, 1, LPR));
+      if (lane >= 2 && row_ok(ph) && i >= 0) td.fb = fused_field(ra, lane, i);
+    }
+  };
+
+  Tile A, B, C;
+  {
+    int b0, e0;
+    bounds(0, b0, e0);
+    bounds(1, nb, ne);
+    load_tile(A, 0, b0, e0);
+  }
+  __syncthreads();    // v's half staged, y's half zeroed
+  for (int ph = 0; ph < nt + 2; ph += 3) {
+    phase(ph, A, C, B);
+    if (ph + 1 < nt + 2) phase(ph + 1, B, A, C);
+    if (ph + 2 < nt + 2) phase(ph + 2, C, B, A);
+  }
+  __syncthreads();    // every wave's scatters are in y's half
+
+  for (int j = threadIdx.x; j < cw; j += kChunkBlock)
+    f.ypart[static_cast<int64_t>(r) * f.ncols + c0 + j] = yh[j];
+  // the terms of v_x . (K v)_x that are not row terms (equality rows,
+  // diagonal): block (r, h) takes the r-th slice of half h
+  if (ra.xdot) {
+    const int j0 = c0 + static_cast<int>(static_cast<int64_t>(cw) * r / f.nrange);
+    const int j1 = c0 + static_cast<int>(static_cast<int64_t>(cw) * (r + 1) / f.nrange);
+    for (int j = j0 + threadIdx.x; j < j1; j += kChunkBlock) {
+      const double vj = vh[j - c0];
+      double e = 0.0;
+      for (int i = 0; i < ra.me; ++i) e += ra.Cm[static_cast<int64_t>(i) * ra.n + j] * ra.we[i];
+      acc += vj * e + ra.qdiag[j] * vj * vj;
+    }
+  }
+  acc = block_sum_nt<kChunkBlock>(acc);
+  if (threadIdx.x == 0) ra.part0[blockIdx.x] = acc;
+}
+
 // ------------------------------------------ tall-skinny dense reduction
 // Block b reduces rows [b*chunk, (b+1)*chunk) of U (n x k, row-major) into
 // part[b][0..k) and of C (me x n) into part[b][k..k+me).  Each wave owns a
@@ -1173,7 +1446,16 @@ __device__ __forceinline__ double cg_q(const CgArgs& a, int i, double pi) {
     for (int c = 0; c < 32; ++c)
       if (c < a.nchunk) y += t[c];
   } else {
-    for (int c = 0; c < a.nchunk; ++c) y += p[c * st];
+    // many partials (the fused pass's row ranges): 32 loads in flight at a
+    // time, summed in range order
+    for (int c0 = 0; c0 < a.nchunk; c0 += 32) {
+      double t[32];
+#pragma unroll
+      for (int c = 0; c < 32; ++c) t[c] = c0 + c < a.nchunk ? p[(c0 + c) * st] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 32; ++c)
+        if (c0 + c < a.nchunk) y += t[c];
+    }
   }
   for (int e = 0; e < a.me; ++e) y += a.Cm[static_cast<int64_t>(e) * a.n + i] * a.we[e];
   y += a.qdiag[i] * pi;
@@ -1634,6 +1916,40 @@ hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   k_fill<<<grid_for(n, kBlock), kBlock, 0, st>>>(dst, n, v);
   return hipGetLastError();
+}
+
+
+// ------------------------------------------ fused pass launcher
+constexpr int kFusedPP = 4;   // entry pairs per lane per batch: 64 entries per row
+
+static uint32_t fused_lds(const FusedArgs& f) {
+  return static_cast<uint32_t>(sizeof(double)) * 2u * f.half;
+}
+
+hipError_t launch_fused(int vk, const FusedArgs& f, const RowArgs& ra, hipStream_t st, const KEvents* ev) {
+  const dim3 g(2 * f.nrange), b(kChunkBlock);
+  const uint32_t lds = fused_lds(f);
+  switch (vk) {
+    case VK_F32: return launch_ev(ev, k_fused<VK_F32, kFusedPP>, g, b, lds, st, f, ra);
+    case VK_BF16: return launch_ev(ev, k_fused<VK_BF16, kFusedPP>, g, b, lds, st, f, ra);
+    case VK_F32X: return launch_ev(ev, k_fused<VK_F32X, kFusedPP>, g, b, lds, st, f, ra);
+    case VK_BF16X: return launch_ev(ev, k_fused<VK_BF16X, kFusedPP>, g, b, lds, st, f, ra);
+    default: return launch_ev(ev, k_fused<VK_F64, kFusedPP>, g, b, lds, st, f, ra);
+  }
+}
+
+hipError_t fused_set_attributes() {
+  const int lds = sizeof(double) * 2 * kFusedHalfMax;
+  hipError_t e = hipSuccess;
+  auto one = [&](const void* fn) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  };
+  one(reinterpret_cast<const void*>(&k_fused<VK_F64, kFusedPP>));
+  one(reinterpret_cast<const void*>(&k_fused<VK_F32, kFusedPP>));
+  one(reinterpret_cast<const void*>(&k_fused<VK_BF16, kFusedPP>));
+  one(reinterpret_cast<const void*>(&k_fused<VK_F32X, kFusedPP>));
+  one(reinterpret_cast<const void*>(&k_fused<VK_BF16X, kFusedPP>));
+  return e;
 }
 
 }  // namespace qpk

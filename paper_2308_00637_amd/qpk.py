@@ -84,11 +84,11 @@ EXPORTS = [
     "qp_init_state", "qp_residuals", "qp_newton_rhs", "qp_kkt_matvec", "kkt_pcg_solve",
     "qp_newton_direction", "qp_step_lengths", "qp_take_step", "ipm_solve", "qp_backward",
     "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_operator_layout",
-    "qp_update_data",
+    "qp_update_data", "qp_fused_layout",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
     "qp_batch_last_error",
 ]
-PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate")
+PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate", "fused")
 
 
 def _load():
@@ -123,6 +123,7 @@ def _load():
         "qp_operator_bytes": (C.c_int, [vp, _i64p, _i64p, _i64p, _i64p, _i64p]),
         "qp_operator_layout": (C.c_int, [vp, _i32p, _i32p, _i32p]),
         "qp_update_data": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "qp_fused_layout": (C.c_int, [vp, _i32p, _i32p, _i32p, _i64p, _i32p]),
         "qp_batch_create": (C.c_int, [C.POINTER(QpDesc), C.c_int32, vp, C.POINTER(vp)]),
         "qp_batch_destroy": (None, [vp]),
         "ipm_solve_batch": (C.c_int, [vp, C.POINTER(IpmOptions), C.c_int32, C.POINTER(IpmInfo)]),
@@ -401,6 +402,16 @@ class QP:
         self._check(LIB.qp_operator_layout(self.h, *arr))
         return {side: {"chunks": int(arr[0][i]), "work_items": int(arr[1][i]),
                        "chunk_cols": int(arr[2][i])} for i, side in enumerate(("row", "col"))}
+
+    def fused_layout(self):
+        """The fused single-read product: active, row ranges, columns of the
+        first half, stored entries, failed (see qp_fused_layout)."""
+        a, rg, hc, fl = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        st = C.c_int64()
+        self._check(LIB.qp_fused_layout(self.h, C.byref(a), C.byref(rg), C.byref(hc), C.byref(st),
+                                        C.byref(fl)))
+        return {"active": bool(a.value), "ranges": int(rg.value), "half_cols": int(hc.value),
+                "stored": int(st.value), "failed": bool(fl.value)}
 
     def backward(self, grad_x, want=("c", "lA", "uA", "b", "w"), opts: Optional[PcgOptions] = None):
         n, sz = self.sizes.n, self.sizes
