@@ -92,6 +92,7 @@ struct qp_handle_s {
     bool failed = false;   // a pair's wait timed out once: two-pass from then on
     int nrows = 0, half = 0, nrange = 0;
     int32_t* range = nullptr;
+    int32_t* rowinfo = nullptr;
     int32_t* rowptr = nullptr;
     uint16_t* col = nullptr;
     double* val = nullptr;
@@ -383,7 +384,7 @@ static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, co
     f.range = h->fz.range; f.rowptr = h->fz.rowptr; f.col = h->fz.col;
     f.val = lo ? h->fz.val_lo : (const void*)h->fz.val;
     f.nstored = (int32_t)h->fz.stored;
-    f.src = v; f.xch = h->fz.xch; f.abort = h->fl + F_FUSEFAIL;
+    f.src = v; f.rowinfo = h->fz.rowinfo; f.xch = h->fz.xch; f.abort = h->fl + F_FUSEFAIL;
     f.epoch = ++h->fz.epoch; f.spin_max = h->fz.spin_max; f.ypart = h->fz.ypart;
     const KEvents ev = prof_slot(h, QP_PROF_FUSED, prof);
     HIPCHK(launch_fused(vk, f, a, h->st, &ev));
@@ -985,7 +986,8 @@ static qp_status build_chunked(qp_handle h, qp_handle_s::Chunked& ck, const std:
 // H = P^T W P when n <= 2 kFusedHalfMax and the operator is large enough for
 // the pass to stream (QPK_FUSED=0 never, =1 whenever the shape allows).
 static qp_status build_fused(qp_handle h, const std::vector<int32_t>& rp, const std::vector<int32_t>& col,
-                             const std::vector<double>& val, int ncols) {
+                             const std::vector<double>& val, int ncols, const std::vector<int32_t>& twin,
+                             const double* lA, const double* uA) {
   const int64_t nrows = (int64_t)rp.size() - 1;
   const char* e = std::getenv("QPK_FUSED");
   const int mode = e ? std::atoi(e) : -1;
@@ -1023,6 +1025,19 @@ static qp_status build_fused(qp_handle h, const std::vector<int32_t>& rp, const 
   fz.half = half;
   fz.nrange = nrange;
   fz.stored = cs.stored;
+  // per row the row of A it carries (its twin, or itself after the rows of
+  // P), with the finite sides of that row as flag bits
+  std::vector<int32_t> info((size_t)nrows, -1);
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = r < h->p_rows ? (twin.empty() ? -1 : twin[r]) : r - h->p_rows;
+    if (i < 0) continue;
+    if (i >= (1 << 29)) {
+      h->err = "fused layout: too many rows of A";
+      return QP_ERR_UNSUPPORTED;
+    }
+    info[r] = (int32_t)i | (std::isfinite(lA[i]) ? (1 << 30) : 0) | (std::isfinite(uA[i]) ? (1 << 29) : 0);
+  }
+  CHK(upload(h, &fz.rowinfo, info.data(), nrows));
   CHK(upload(h, &fz.range, range.data(), (int64_t)range.size()));
   CHK(upload(h, &fz.rowptr, cs.rowptr.data(), (int64_t)cs.rowptr.size()));
   CHK(upload(h, &fz.col, cs.col.data(), cs.stored));
@@ -1272,12 +1287,12 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
     CHK(build_chunked(h, h->ck_x, xrp_p, scol_p, xval_p, (int)p_rows, kChunkCols / 2, 1, false,
                       "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));
     CHK(upload(h, &h->twin, twin.data(), (int64_t)twin.size()));
-    CHK(build_fused(h, rrp_p, rcol, rval, (int)n));
+    CHK(build_fused(h, rrp_p, rcol, rval, (int)n, twin, d->lA, d->uA));
   } else {
     if (h->nRP > 0)
       CHK(build_chunked(h, h->ck_r, rrp, rcol, rval, (int)n, kChunkCols, 0, true, "QPK_CHUNK_COLS_R",
                         "QPK_LPR_R", "QPK_KV_R"));
-    if (h->nRP > 0 && want_ck_x) CHK(build_fused(h, rrp, rcol, rval, (int)n));
+    if (h->nRP > 0 && want_ck_x) CHK(build_fused(h, rrp, rcol, rval, (int)n, {}, d->lA, d->uA));
     if (want_ck_x)
       CHK(build_chunked(h, h->ck_x, xrp, scol, xval, (int)(p_rows + m), kChunkCols / 2, 1, false,
                         "QPK_CHUNK_COLS_X", "QPK_LPR_X", "QPK_KV_X"));

@@ -198,7 +198,8 @@ hipError_t chunked_set_attributes();
 // [half, ncols)); a pair of blocks per row range, one per half, exchanges the
 // half dots of each row through xch.
 constexpr int kFusedLpr = 8;                          // lanes per row
-constexpr int kFusedHalfMax = (163840 - 256) / 16;    // columns per half (LDS: v's and y's half)
+constexpr int kFusedOwn = (kChunkBlock / 64) * 3 * (64 / kFusedLpr);   // float64 dots kept in LDS
+constexpr int kFusedHalfMax = (163840 - 256 - 8 * kFusedOwn) / 16;    // columns per half
 struct FusedArgs {
   int32_t nrows, ncols;      // rows of the row operator, n
   int32_t half;              // columns of half 0 (even, >= ncols - half)
@@ -209,6 +210,8 @@ struct FusedArgs {
   const void* val;
   int32_t nstored;
   const double* src;         // gathered x-space vector (ncols)
+  const int32_t* rowinfo;    // per row: index of the row of A it carries | bit 30 finite
+                             // lower side | bit 29 finite upper side, or -1
   double* xch;               // 2 parities x 2 halves x nrows half dots (all bits set = empty)
   int* abort;                // sticky: a wait timed out, the product is invalid
   unsigned long long epoch;  // launch count (its parity picks the exchange slots)

@@ -853,18 +853,48 @@ __global__ __launch_bounds__(kBlock) void k_chunk_epilogue_row(ChunkArgs b, RowA
 // product is then invalid and the host redoes the work with the two-pass
 // kernels.
 
+// Exchanges within a group of 8 lanes (a half row of the DPP unit), done by
+// the VALU's data-parallel permutes rather than through the LDS crossbar:
+// quad_perm moves values within 4 lanes, row_half_mirror maps lane i of
+// 8 to lane 7 - i.
+constexpr int kDppHalfMirror = 0x141;
+constexpr int dpp_quad(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const i2v v = __builtin_bit_cast(i2v, x);
+  i2v o;
+  o.x = __builtin_amdgcn_update_dpp(0, v.x, CTRL, 0xf, 0xf, false);
+  o.y = __builtin_amdgcn_update_dpp(0, v.y, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, o);
+}
+// Sum over the 8 lanes of the group, the same bits on every lane.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_f64<dpp_quad(1, 0, 3, 2)>(v);
+  v += dpp_f64<dpp_quad(2, 3, 0, 1)>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  return v;
+}
+// Lane J's value of the group, on every lane of the group.
+template <int J>
+__device__ __forceinline__ double group8_bcast(double x) {
+  const double y = dpp_f64<dpp_quad(J & 3, J & 3, J & 3, J & 3)>(x);   // lane J mod 4 of each quad
+  const double z = dpp_f64<kDppHalfMirror>(y);                       // the other quad's
+  const bool upper = (threadIdx.x & 4) != 0;
+  return upper == (J >= 4) ? y : z;
+}
+
 // Row data of the epilogue, loaded ahead by role: in a tile's load phase
 // lane 0 of the row's group fetches w_r (0 for a row of A) and lane 1 the
-// index i_r of the row of A the row carries (its twin for a row of P, or
-// itself; -1 for none); after the tile's dot lanes 2..7 fetch that row of
-// A's lA, uA, v_lo, v_up, d_lo, d_up.
+// row's rowinfo word: the index i_r of the row of A the row carries (its
+// twin for a row of P, or itself), with bit 30 set when that row has a
+// finite lower side and bit 29 a finite upper side, or -1 for none; after
+// the tile's dot lanes 2..5 fetch that row of A's v_lo, v_up, d_lo, d_up.
+constexpr int kRowLo = 1 << 30, kRowHi = 1 << 29, kRowIdx = kRowHi - 1;
 __device__ __forceinline__ double fused_field(const RowArgs& a, int role, int i) {
   switch (role) {
-    case 2: return a.lA[i];
-    case 3: return a.uA[i];
-    case 4: return a.vl[a.me + i];
-    case 5: return a.vl[a.me + a.m + i];
-    case 6: return a.dl[a.me + i];
+    case 2: return a.vl[a.me + i];
+    case 3: return a.vl[a.me + a.m + i];
+    case 4: return a.dl[a.me + i];
     default: return a.dl[a.me + a.m + i];
   }
 }
@@ -890,6 +920,9 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
   double* yh = lds + f.half;           // y_x[c0, c0 + cw)
   const int R0 = f.range[r], R1 = f.range[r + 1];
   const int wave = static_cast<int>(threadIdx.x) >> 6;
+  // this half's dots of the wave's rows, by tile mod 3 (kept here rather than
+  // in registers from the dot to the scatter two phases later)
+  double* owns = lds + 2 * f.half + wave * 3 * GW;
   const int g = (static_cast<int>(threadIdx.x) & 63) / LPR;   // group in the wave
   const int lane = threadIdx.x & (LPR - 1);
   // wave tile k holds rows R0 + (k NW + wave) GW + g
@@ -915,8 +948,7 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
     LT vx[PP], vy[PP];
     int beg, end;
     double fb;        // this lane's epilogue field (see fused_field)
-    double own;       // lane 0: this half's dot of the group's row
-    double xo;        // lane 0: the partner's half dot, or the sentinel
+    double xo;        // the partner's half dot, or the sentinel (every lane)
   };
   auto load_batch = [&](int base, int end, uint32_t* cc, LT* vx, LT* vy) {
 #pragma unroll
@@ -942,8 +974,7 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
     if (row_ok(k)) {
       const int row = row_of(k);
       if (lane == 0) tl.fb = row < ra.p_rows ? ra.w[row] : 0.0;
-      if (lane == 1)
-        tl.fb = static_cast<double>(row < ra.p_rows ? (ra.twin ? ra.twin[row] : -1) : row - ra.p_rows);
+      if (lane == 1) tl.fb = static_cast<double>(f.rowinfo[row]);
     }
     tl.beg = beg;
     tl.end = end;
@@ -966,7 +997,7 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
   auto scatter_tile = [&](Tile& tl, int k) {
     const bool valid = row_ok(k);
     double t = 0.0;
-    if (valid && lane == 0) {
+    if (valid) {     // every lane of the group, on the same slot
       const int row = row_of(k);
       unsigned long long bits = __builtin_bit_cast(unsigned long long, tl.xo);
       for (int spin = 0; bits == kFusedEmpty && !abandoned; ++spin) {
@@ -983,21 +1014,22 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
                                   __hip_atomic_load(xother + row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       }
       const double o = bits == kFusedEmpty ? 0.0 : __builtin_bit_cast(double, bits);
-      __hip_atomic_store(xother + row, __builtin_bit_cast(double, kFusedEmpty), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      t = h == 0 ? tl.own + o : o + tl.own;     // half 0 first on both sides
+      if (lane == 0)
+        __hip_atomic_store(xother + row, __builtin_bit_cast(double, kFusedEmpty), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      const double own = owns[(k % 3) * GW + g];
+      t = h == 0 ? own + o : o + own;     // half 0 first on both sides
     }
-    const double w = __shfl(tl.fb, 0, LPR);
-    const int i = static_cast<int>(__shfl(tl.fb, 1, LPR));
-    const double lA = __shfl(tl.fb, 2, LPR), uA = __shfl(tl.fb, 3, LPR);
-    const double vlo = __shfl(tl.fb, 4, LPR), vup = __shfl(tl.fb, 5, LPR);
-    const double dlo = __shfl(tl.fb, 6, LPR), dup = __shfl(tl.fb, 7, LPR);
-    t = __shfl(t, 0, LPR);
+    const double w = group8_bcast<0>(tl.fb);
+    const int info = static_cast<int>(group8_bcast<1>(tl.fb));
+    const double vlo = group8_bcast<2>(tl.fb), vup = group8_bcast<3>(tl.fb);
+    const double dlo = group8_bcast<4>(tl.fb), dup = group8_bcast<5>(tl.fb);
     if (!valid) return;
     const double uv = w * t;
     double wa = 0.0;
-    if (i >= 0) {
-      const bool hl = has_lo(lA), hu = has_hi(uA);
+    if (info >= 0) {
+      const int i = info & kRowIdx;
+      const bool hl = (info & kRowLo) != 0, hu = (info & kRowHi) != 0;
       wa = (hl ? 2.0 * t / dlo + vlo : 0.0) - (hu ? -2.0 * t / dup + vup : 0.0);
       if (h == 0 && lane == 0) {
         // the lam-part of K v for this row of A, and its terms of p.q
@@ -1025,7 +1057,7 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
   auto phase = [&](int ph, Tile& td, Tile& tw, Tile& tsl) {
     if (ph >= 2) scatter_tile(tsl, ph - 2);
     tw.xo = 0.0;
-    if (lane == 0 && row_ok(ph - 1))
+    if (row_ok(ph - 1))
       tw.xo = __hip_atomic_load(xother + row_of(ph - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int cb = nb, ce = ne;
     bounds(ph + 2, nb, ne);
@@ -1047,13 +1079,13 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
           t += static_cast<Acc>(y2[k]) * static_cast<Acc>(vh[c2[k] >> 16]);
         }
       }
-      t = group_sum<LPR>(t);
-      td.own = static_cast<double>(t);
+      const double own = group8_sum(static_cast<double>(t));
+      if (lane == 0) owns[(ph % 3) * GW + g] = own;
       if (lane == 0 && row_ok(ph))
-        __hip_atomic_store(xown + row_of(ph), td.own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // the row of A this row carries: lanes 2..7 fetch its fields
-      const int i = static_cast<int>(__shfl(td.fb, 1, LPR));
-      if (lane >= 2 && row_ok(ph) && i >= 0) td.fb = fused_field(ra, lane, i);
+        __hip_atomic_store(xown + row_of(ph), own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // the row of A this row carries: lanes 2..5 fetch its fields
+      const int info = static_cast<int>(group8_bcast<1>(td.fb));
+      if (lane >= 2 && lane <= 5 && row_ok(ph) && info >= 0) td.fb = fused_field(ra, lane, info & kRowIdx);
     }
   };
 
@@ -1923,7 +1955,7 @@ hipError_t launch_fill(double* dst, int64_t n, double v, hipStream_t st) {
 constexpr int kFusedPP = 4;   // entry pairs per lane per batch: 64 entries per row
 
 static uint32_t fused_lds(const FusedArgs& f) {
-  return static_cast<uint32_t>(sizeof(double)) * 2u * f.half;
+  return static_cast<uint32_t>(sizeof(double)) * (2u * f.half + kFusedOwn);
 }
 
 hipError_t launch_fused(int vk, const FusedArgs& f, const RowArgs& ra, hipStream_t st, const KEvents* ev) {
@@ -1939,7 +1971,7 @@ hipError_t launch_fused(int vk, const FusedArgs& f, const RowArgs& ra, hipStream
 }
 
 hipError_t fused_set_attributes() {
-  const int lds = sizeof(double) * 2 * kFusedHalfMax;
+  const int lds = sizeof(double) * (2 * kFusedHalfMax + kFusedOwn);
   hipError_t e = hipSuccess;
   auto one = [&](const void* fn) {
     if (e == hipSuccess) e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
