@@ -316,6 +316,30 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
 qp_status qp_batch_get_solution(qp_batch b, int32_t i, double* x, double* lam, double* s);
 const char* qp_batch_last_error(qp_batch b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one dense QP
+ *     min 1/2 x^T H x + c^T x  s.t.  lA <= A x <= uA,  lx <= x <= ux
+ * solved by the batched solver's kernel (the same steps and defaults as
+ * ipm_solve_batch on a batch of this one instance, float64 operators), with
+ * every workspace in a fixed device array of the library: 16 MiB per GPU,
+ * set aside until the process ends, which holds problems whose 29 n + 31 m
+ * float64 values of workspace fit in it (n = m = 34,000 does; larger sizes
+ * give QP_ERR_ARG before anything is launched).  The
+ * call allocates nothing.  Inputs are DEVICE pointers read in place: H (n*n
+ * row-major), c (n), A (m*n row-major), lA, uA (m; A, lA, uA may be NULL when
+ * m = 0), lx, ux (n, or NULL for no bounds); bounds are checked on the device
+ * (QP_ERR_ARG), NaN or Inf in H, A or c gives QP_ERR_NUMERIC.  Outputs x (n),
+ * lam, s (2m + 2n, layouts as for a handle with me = 0) are DEVICE pointers,
+ * each may be NULL; info (HOST) must not be NULL, and filling it synchronises
+ * the stream (hipStream_t, NULL = default).  Of o only the IPM constants and
+ * pcg.tol / pcg.maxit are read; warm_start is not supported.  Every call on
+ * one GPU uses that GPU's array: calls that overlap on a GPU (other host
+ * threads, other streams) race.  Error messages: qp_batch_last_error(NULL). */
+qp_status ipm_solve_dense_noalloc(int64_t n, int64_t m, const double* H, const double* c,
+                                  const double* A, const double* lA, const double* uA,
+                                  const double* lx, const double* ux, const ipm_options* o,
+                                  double* x, double* lam, double* s, ipm_info* info, void* stream);
+
 /* Replace problem data in place (DEVICE pointers, NULL = keep): the linear
  * term c (n), the row bounds lA, uA (m, +-INFINITY allowed, with the same
  * finite/infinite pattern as at creation), the equality right-hand side b

@@ -18,8 +18,11 @@
 #include "../../include/qpk.h"
 
 #include <algorithm>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -31,7 +34,8 @@ constexpr int kBW = kBB / 64;        // waves per workgroup
 
 struct BInst {
   int32_t n, m, k, hkind;            // hkind: 0 dense H, 1 low rank
-  int64_t a_off, h_off;              // element offsets of A and of H (or U) in the value pool
+  const void* A;                     // m x n row-major, in the operator precision
+  const void* H;                     // n x n (or U, n x k) row-major, likewise
   int64_t v_off;                     // offset of the instance's float64 block
 };
 
@@ -72,7 +76,6 @@ struct BArgs {
   const int32_t* order;
   int32_t count;
   int32_t* next;
-  const T* vals;
   double* vec;
   BResult* out;
   BOpts o;
@@ -168,8 +171,9 @@ struct Inst {
   const T* H;  // dense H or U
   double* v;
   BLayout L;
-  __device__ Inst(const BInst& bi, const T* vals, double* vec)
-      : n(bi.n), m(bi.m), k(bi.k), hk(bi.hkind), A(vals + bi.a_off), H(vals + bi.h_off),
+  __device__ Inst(const BInst& bi, double* vec)
+      : n(bi.n), m(bi.m), k(bi.k), hk(bi.hkind), A(static_cast<const T*>(bi.A)),
+        H(static_cast<const T*>(bi.H)),
         v(vec + bi.v_off), L(bi.n, bi.m, bi.k) {}
   __device__ double* P(int64_t off) const { return v + off; }
 };
@@ -198,9 +202,9 @@ __device__ __forceinline__ void hess_apply(const Inst<T>& I, const double* x, do
 // Residual stack (eq. 3 with the bound rows) and its norms; returns
 // {stacked, primal, dual, compl}.
 template <typename T>
-__device__ __noinline__ void residuals(const BInst* bi, const T* vals, double* vec, double mu,
+__device__ __noinline__ void residuals(const BInst* bi, double* vec, double mu,
                                     double* nrm) {
-  const Inst<T> I(*bi, vals, vec);
+  const Inst<T> I(*bi, vec);
   const int n = I.n, m = I.m;
   const double *x = I.P(I.L.x), *lam = I.P(I.L.lam), *s = I.P(I.L.s);
   const double *lA = I.P(I.L.lA), *uA = I.P(I.L.uA), *lx = I.P(I.L.lx), *ux = I.P(I.L.ux);
@@ -252,8 +256,8 @@ __device__ __noinline__ void residuals(const BInst* bi, const T* vals, double* v
 
 // D, the eq. 9 right-hand side, diag(K) and Q's diagonal (eqs. 8, 9).
 template <typename T>
-__device__ __noinline__ void newton_system(const BInst* bi, const T* vals, double* vec, double mu) {
-  const Inst<T> I(*bi, vals, vec);
+__device__ __noinline__ void newton_system(const BInst* bi, double* vec, double mu) {
+  const Inst<T> I(*bi, vec);
   const int n = I.n, m = I.m;
   const double *lam = I.P(I.L.lam), *s = I.P(I.L.s), *res = I.P(I.L.res);
   const double *lA = I.P(I.L.lA), *uA = I.P(I.L.uA), *lx = I.P(I.L.lx), *ux = I.P(I.L.ux);
@@ -339,9 +343,9 @@ __device__ __forceinline__ double kkt_apply(const Inst<T>& I, const double* p, d
 
 // Jacobi PCG on eq. 9 into sol; returns iterations (negative: status code).
 template <typename T>
-__device__ __noinline__ int pcg(const BInst* bi, const T* vals, double* vec, double tol, int maxit,
+__device__ __noinline__ int pcg(const BInst* bi, double* vec, double tol, int maxit,
                                int* converged_out) {
-  const Inst<T> I(*bi, vals, vec);
+  const Inst<T> I(*bi, vec);
   const int N = I.n + 2 * I.m;
   double *x = I.P(I.L.sol), *r = I.P(I.L.r), *z = I.P(I.L.z), *p = I.P(I.L.p), *q = I.P(I.L.q);
   const double *rhs = I.P(I.L.rhs), *jd = I.P(I.L.jd);
@@ -388,9 +392,9 @@ __device__ __noinline__ int pcg(const BInst* bi, const T* vals, double* vec, dou
 
 // Recovery (eq. 7) and the ratio test (eq. 10): returns alpha_x, alpha_lam.
 template <typename T>
-__device__ __noinline__ void recover_ratio(const BInst* bi, const T* vals, double* vec, double gamma,
+__device__ __noinline__ void recover_ratio(const BInst* bi, double* vec, double gamma,
                                         double* alphas) {
-  const Inst<T> I(*bi, vals, vec);
+  const Inst<T> I(*bi, vec);
   double ax, al;
   const int n = I.n, m = I.m;
   const double *lam = I.P(I.L.lam), *s = I.P(I.L.s), *res = I.P(I.L.res);
@@ -443,7 +447,7 @@ __device__ __noinline__ void recover_ratio(const BInst* bi, const T* vals, doubl
 
 template <typename T>
 __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
-  const Inst<T> I(a.inst[id], a.vals, a.vec);
+  const Inst<T> I(a.inst[id], a.vec);
   const int n = I.n, m = I.m;
   const BOpts& o = a.o;
   double *x = I.P(I.L.x), *lam = I.P(I.L.lam), *s = I.P(I.L.s), *t = I.P(I.L.t);
@@ -486,10 +490,10 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
   int64_t total = 0;
   const BInst* bi = a.inst + id;
   for (it = 1; it <= o.max_iter; ++it) {
-    residuals<T>(bi, a.vals, a.vec, mu, nrm);
-    newton_system<T>(bi, a.vals, a.vec, mu);
+    residuals<T>(bi, a.vec, mu, nrm);
+    newton_system<T>(bi, a.vec, mu);
     int conv = 0;
-    const int pit = pcg<T>(bi, a.vals, a.vec, o.cg_tol, o.cg_maxit, &conv);
+    const int pit = pcg<T>(bi, a.vec, o.cg_tol, o.cg_maxit, &conv);
     if (pit < 0) {
       status = pit;
       break;
@@ -497,7 +501,7 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
     total += pit;
     if (!conv) ++hits;
     double al2[2];
-    recover_ratio<T>(bi, a.vals, a.vec, o.gamma, al2);
+    recover_ratio<T>(bi, a.vec, o.gamma, al2);
     const double ax = al2[0], al = al2[1];
     const double *dx = I.P(I.L.sol), *dlam = I.P(I.L.sol) + n, *ds = I.P(I.L.ds);
     for (int j = threadIdx.x; j < n; j += kBB) x[j] += ax * dx[j];
@@ -506,7 +510,7 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
       lam[q] += al * dlam[q];
     }
     __syncthreads();
-    residuals<T>(bi, a.vals, a.vec, mu, nrm);
+    residuals<T>(bi, a.vec, mu, nrm);
     if (!isfinite(nrm[0])) {
       status = QP_ERR_NUMERIC_CODE;
       break;
@@ -548,6 +552,75 @@ __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
     __syncthreads();
     if (q >= a.count) break;
     solve_one(a, __builtin_amdgcn_readfirstlane(a.order[q]));
+  }
+}
+
+// ---------------------------------------- allocation-free single dense solve
+// The one instance's descriptor, queue counter, result and float64 block live
+// in a fixed device array of the library, `scratch` (one per GPU, held until
+// the process ends); H and A are read where the caller keeps them.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+struct NaHead {
+  BInst inst;
+  int32_t order, next;
+  BResult out;
+  int32_t bad, pad;
+};
+constexpr size_t kNaHeadBytes = 256 * ((sizeof(NaHead) + 255) / 256);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Fills the instance's block from the caller's vectors (every entry, so a
+// previous call's contents never leak in), checks the bounds, and writes the
+// descriptor; an invalid problem leaves the queue empty, so the solve kernel
+// exits at once.  One workgroup.
+__global__ __launch_bounds__(kBB) void k_noalloc_setup(unsigned char* base, int n, int m, const double* H,
+                                                       const double* A, const double* c, const double* lA,
+                                                       const double* uA, const double* lx, const double* ux) {
+  NaHead* hd = reinterpret_cast<NaHead*>(base);
+  double* v = reinterpret_cast<double*>(base + kNaHeadBytes);
+  const BLayout L(n, m, 0);
+  for (int64_t i = threadIdx.x; i < L.total; i += kBB) v[i] = 0.0;
+  __syncthreads();
+  int bad = 0;
+  for (int j = threadIdx.x; j < n; j += kBB) {
+    const double l = lx ? lx[j] : -INFINITY, u = ux ? ux[j] : INFINITY;
+    if (isnan(l) || isnan(u) || l == INFINITY || u == -INFINITY || (isfinite(l) && isfinite(u) && !(l < u)))
+      bad = 1;
+    v[L.c + j] = c[j];
+    v[L.lx + j] = l;
+    v[L.ux + j] = u;
+  }
+  for (int r = threadIdx.x; r < m; r += kBB) {
+    const double l = lA[r], u = uA[r];
+    if (isnan(l) || isnan(u) || l == INFINITY || u == -INFINITY || l > u) bad = 1;
+    v[L.lA + r] = l;
+    v[L.uA + r] = u;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) {
+    hd->inst.n = n;
+    hd->inst.m = m;
+    hd->inst.k = 0;
+    hd->inst.hkind = 0;
+    hd->inst.A = A;
+    hd->inst.H = H;
+    hd->inst.v_off = 0;
+    hd->order = 0;
+    hd->next = bad ? 1 : 0;
+    hd->bad = bad;
+    hd->out = BResult{};
+  }
+}
+
+__global__ __launch_bounds__(kBB) void k_noalloc_out(const unsigned char* base, int n, int m, double* x,
+                                                     double* lam, double* s) {
+  const double* v = reinterpret_cast<const double*>(base + kNaHeadBytes);
+  const BLayout L(n, m, 0);
+  const int nl = 2 * m + 2 * n;
+  for (int i = blockIdx.x * kBB + threadIdx.x; i < nl; i += gridDim.x * kBB) {
+    if (x && i < n) x[i] = v[L.x + i];
+    if (lam) lam[i] = v[L.lam + i];
+    if (s) s[i] = v[L.s + i];
   }
 }
 
@@ -604,6 +677,7 @@ static qp_status batch_create_impl(qp_batch b, const qp_desc* ds, int32_t count)
   const int vb = b->f32 ? 4 : 8;
   int64_t vals = 0, vecs = 0;
   b->inst.resize(count);
+  std::vector<int64_t> a_off(count), h_off(count);   // element offsets in the value pool
   for (int i = 0; i < count; ++i) {
     const qp_desc& d = ds[i];
     if (d.precision != prec) return bad(i, "all instances need the same precision");
@@ -634,8 +708,8 @@ static qp_status batch_create_impl(qp_batch b, const qp_desc* ds, int32_t count)
     BInst& I = b->inst[i];
     I.n = (int)d.n; I.m = (int)d.m; I.k = d.h_kind == QP_H_LOWRANK ? (int)d.k : 0;
     I.hkind = d.h_kind == QP_H_LOWRANK ? 1 : 0;
-    I.a_off = vals; vals += d.m * d.n;
-    I.h_off = vals; vals += I.hkind ? d.n * d.k : d.n * d.n;
+    a_off[i] = vals; vals += d.m * d.n;
+    h_off[i] = vals; vals += I.hkind ? d.n * d.k : d.n * d.n;
     I.v_off = vecs; vecs += BLayout(I.n, I.m, I.k).total;
   }
   // host staging, then one upload each
@@ -653,8 +727,8 @@ static qp_status batch_create_impl(qp_batch b, const qp_desc* ds, int32_t count)
   for (int i = 0; i < count; ++i) {
     const qp_desc& d = ds[i];
     const BInst& I = b->inst[i];
-    if (d.m > 0 && !put(I.a_off, d.A, d.m * d.n)) return bad(i, "A not finite");
-    if (I.hkind ? !put(I.h_off, d.U, d.n * d.k) : !put(I.h_off, d.H, d.n * d.n)) return bad(i, "H not finite");
+    if (d.m > 0 && !put(a_off[i], d.A, d.m * d.n)) return bad(i, "A not finite");
+    if (I.hkind ? !put(h_off[i], d.U, d.n * d.k) : !put(h_off[i], d.H, d.n * d.n)) return bad(i, "H not finite");
     const BLayout L(I.n, I.m, I.k);
     double* v = hv.data() + I.v_off;
     for (int64_t j = 0; j < d.n; ++j) {
@@ -681,6 +755,10 @@ static qp_status batch_create_impl(qp_batch b, const qp_desc* ds, int32_t count)
   BCHK(hipMalloc(&b->d_vals, (size_t)std::max<int64_t>(vals, 1) * vb));
   BCHK(hipMalloc((void**)&b->d_vec, sizeof(double) * std::max<int64_t>(vecs, 1)));
   BCHK(hipMalloc((void**)&b->d_out, sizeof(BResult) * count));
+  for (int i = 0; i < count; ++i) {
+    b->inst[i].A = static_cast<const char*>(b->d_vals) + a_off[i] * vb;
+    b->inst[i].H = static_cast<const char*>(b->d_vals) + h_off[i] * vb;
+  }
   BCHK(hipMemcpyAsync(b->d_inst, b->inst.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, b->st));
   BCHK(hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, b->st));
   if (vals > 0)
@@ -743,10 +821,10 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
   BCHK(hipEventCreate(&e1));
   BCHK(hipEventRecord(e0, b->st));
   if (b->f32) {
-    BArgs<float> a{b->d_inst, b->d_order, b->count, b->d_next, (const float*)b->d_vals, b->d_vec, b->d_out, bo};
+    BArgs<float> a{b->d_inst, b->d_order, b->count, b->d_next, b->d_vec, b->d_out, bo};
     k_batch_ipm<float><<<grid, kBB, 0, b->st>>>(a);
   } else {
-    BArgs<double> a{b->d_inst, b->d_order, b->count, b->d_next, (const double*)b->d_vals, b->d_vec, b->d_out, bo};
+    BArgs<double> a{b->d_inst, b->d_order, b->count, b->d_next, b->d_vec, b->d_out, bo};
     k_batch_ipm<double><<<grid, kBB, 0, b->st>>>(a);
   }
   BCHK(hipGetLastError());
@@ -779,6 +857,121 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
   }
   if (worst != QP_OK) b->err = "at least one instance stopped on a numerical error (see its info)";
   return worst;
+}
+
+// Per-device address of `scratch`, looked up once per device with that
+// device current (the array's name in host code is not a device address).
+static std::mutex g_scratch_mu;
+static void* g_scratch[64] = {};
+
+static qp_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= 64) {
+    g_batch_error = "device index out of range";
+    return QP_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      g_batch_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return QP_ERR_HIP;
+    }
+    g_scratch[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch[dev]);
+  return QP_OK;
+}
+
+#define NCHK(expr)                                                             \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      g_batch_error = std::string(#expr) + ": " + hipGetErrorString(e_);       \
+      return QP_ERR_HIP;                                                       \
+    }                                                                          \
+  } while (0)
+
+qp_status ipm_solve_dense_noalloc(int64_t n, int64_t m, const double* H, const double* c,
+                                  const double* A, const double* lA, const double* uA,
+                                  const double* lx, const double* ux, const ipm_options* o,
+                                  double* x, double* lam, double* s, ipm_info* info, void* stream) {
+  if (n < 1 || m < 0 || n > INT32_MAX / 8 || m > INT32_MAX / 8 || !H || !c || !info ||
+      (m > 0 && (!A || !lA || !uA))) {
+    g_batch_error = "need n >= 1, m >= 0, H, c, info, and A, lA, uA when m > 0";
+    return QP_ERR_ARG;
+  }
+  const size_t need = kNaHeadBytes + sizeof(double) * (size_t)BLayout(n, m, 0).total;
+  if (need > kScratchBytes) {
+    g_batch_error = "problem needs " + std::to_string(need) + " bytes of workspace; the allocation-free "
+                    "solve has " + std::to_string(kScratchBytes) + " (it takes 29 n + 31 m float64 values)";
+    return QP_ERR_ARG;
+  }
+  ipm_options opt;
+  qp_default_ipm_options(&opt);
+  if (o) opt = *o;
+  if (opt.warm_start) {
+    g_batch_error = "the allocation-free solve always starts from the default point";
+    return QP_ERR_UNSUPPORTED;
+  }
+  BOpts bo{};
+  bo.gamma = opt.gamma; bo.mu0 = opt.mu0; bo.mu_tol = opt.mu_tol; bo.mu_div = opt.mu_div;
+  bo.max_iter = opt.max_iter;
+  bo.cg_tol = opt.pcg.tol > 0 ? opt.pcg.tol : 1e-7;
+  bo.cg_maxit = opt.pcg.maxit > 0 ? opt.pcg.maxit : 5000;
+  if (!(bo.gamma > 0 && bo.gamma < 1) || !(bo.mu0 > 0) || !(bo.mu_div > 1) || bo.max_iter < 1) {
+    g_batch_error = "invalid ipm_options";
+    return QP_ERR_ARG;
+  }
+  int dev = 0;
+  NCHK(hipGetDevice(&dev));
+  unsigned char* base = nullptr;
+  qp_status st = scratch_address(dev, &base);
+  if (st != QP_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  NaHead* hd = reinterpret_cast<NaHead*>(base);
+  k_noalloc_setup<<<1, kBB, 0, hs>>>(base, (int)n, (int)m, H, A, c, lA, uA, lx, ux);
+  NCHK(hipGetLastError());
+  BArgs<double> a{&hd->inst, &hd->order, 1, &hd->next, reinterpret_cast<double*>(base + kNaHeadBytes),
+                  &hd->out, bo};
+  k_batch_ipm<double><<<1, kBB, 0, hs>>>(a);
+  NCHK(hipGetLastError());
+  if (x || lam || s) {
+    const int nl = (int)(2 * m + 2 * n);
+    k_noalloc_out<<<std::min(256, (nl + kBB - 1) / kBB), kBB, 0, hs>>>(base, (int)n, (int)m, x, lam, s);
+    NCHK(hipGetLastError());
+  }
+  BResult r{};
+  int32_t bad = 0;
+  NCHK(hipMemcpyAsync(&r, &hd->out, sizeof(BResult), hipMemcpyDeviceToHost, hs));
+  NCHK(hipMemcpyAsync(&bad, &hd->bad, sizeof(int32_t), hipMemcpyDeviceToHost, hs));
+  NCHK(hipStreamSynchronize(hs));
+  if (bad) {
+    g_batch_error = "invalid bounds (NaN, an infinite side on the wrong side, or lower above upper)";
+    return QP_ERR_ARG;
+  }
+  std::memset(info, 0, sizeof(*info));
+  info->result = r.status == QP_IPM_CONVERGED ? QP_IPM_CONVERGED : QP_IPM_MAX_ITER;
+  info->iterations = r.iterations;
+  info->total_cg_iters = r.total_cg;
+  info->cg_maxiter_hits = r.cg_hits;
+  info->mu_final = r.mu_final;
+  info->rnorm = r.rnorm;
+  info->primal = r.primal;
+  info->dual = r.dual;
+  info->compl_ = r.compl_;
+  info->objective = r.objective;
+  info->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (r.status == QP_ERR_NOT_SPD_CODE) {
+    g_batch_error = "PCG met a non-positive curvature p^T K p";
+    return QP_ERR_NOT_SPD;
+  }
+  if (r.status == QP_ERR_NUMERIC_CODE) {
+    g_batch_error = "NaN or Inf met in a reduction";
+    return QP_ERR_NUMERIC;
+  }
+  return QP_OK;
 }
 
 qp_status qp_batch_get_solution(qp_batch b, int32_t i, double* x, double* lam, double* s) {

@@ -86,7 +86,7 @@ EXPORTS = [
     "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_operator_layout",
     "qp_update_data", "qp_fused_layout",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
-    "qp_batch_last_error",
+    "qp_batch_last_error", "ipm_solve_dense_noalloc",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate", "fused")
 
@@ -129,6 +129,8 @@ def _load():
         "ipm_solve_batch": (C.c_int, [vp, C.POINTER(IpmOptions), C.c_int32, C.POINTER(IpmInfo)]),
         "qp_batch_get_solution": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "qp_batch_last_error": (C.c_char_p, [vp]),
+        "ipm_solve_dense_noalloc": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
+                                              C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -474,3 +476,26 @@ class QPBatch:
         if st != QP_OK:
             raise QPError(st, LIB.qp_batch_last_error(self.h).decode())
         return x, lam, s
+
+
+def ipm_solve_dense_noalloc(H, c, A=None, lA=None, uA=None, lx=None, ux=None,
+                            opts: Optional[IpmOptions] = None, want_state: bool = True):
+    """The allocation-free dense solve (see include/qpk.h): every argument a
+    float64 device tensor (or None), the outputs allocated here by torch, the
+    library allocates nothing.  Returns dict(x, lam, s, info)."""
+    import torch
+    n = int(c.shape[0])
+    m = 0 if A is None else int(A.shape[0])
+    info = IpmInfo()
+    if want_state:
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        lam = torch.empty(2 * m + 2 * n, dtype=torch.float64, device="cuda")
+        s = torch.empty(2 * m + 2 * n, dtype=torch.float64, device="cuda")
+    else:
+        x = lam = s = None
+    st = LIB.ipm_solve_dense_noalloc(n, m, _dev(H), _dev(c), _dev(A), _dev(lA), _dev(uA), _dev(lx),
+                                     _dev(ux), C.byref(opts) if opts is not None else None,
+                                     _dev(x), _dev(lam), _dev(s), C.byref(info), _stream())
+    if st not in (QP_OK, QP_ERR_NOT_SPD, QP_ERR_NUMERIC):
+        raise QPError(st, LIB.qp_batch_last_error(None).decode())
+    return dict(x=x, lam=lam, s=s, info=info, status=st)
