@@ -938,9 +938,23 @@ __global__ __launch_bounds__(kChunkBlock) void k_fused(FusedArgs f, RowArgs ra) 
   double* xother = xbase + static_cast<int64_t>(h ^ 1) * f.nrows;
   using LT = decltype(ldv(val, 0));
 
-  for (int i = threadIdx.x; i < cw; i += kChunkBlock) {
-    vh[i] = f.src[c0 + i];
-    yh[i] = 0.0;
+  {
+    // stage v's half: every 16-byte load issued before the first LDS write,
+    // so the block waits for one memory latency (c0 and the half are even)
+    constexpr int SP = (kFusedHalfMax + 2 * kChunkBlock - 1) / (2 * kChunkBlock);
+    const __amdgpu_buffer_rsrc_t rsv = rsrc(f.src + c0, 8u * static_cast<uint32_t>(cw));
+    double2 st[SP];
+#pragma unroll
+    for (int k = 0; k < SP; ++k)
+      st[k] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                              rsv, 16u * (threadIdx.x + k * kChunkBlock), 0, 0));
+    for (int i = threadIdx.x; i < cw; i += kChunkBlock) yh[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int i2 = threadIdx.x + k * kChunkBlock;
+      if (2 * i2 + 1 < cw) reinterpret_cast<double2*>(vh)[i2] = st[k];
+    }
+    if ((cw & 1) && threadIdx.x == 0) vh[cw - 1] = f.src[c0 + cw - 1];
   }
 
   struct Tile {
