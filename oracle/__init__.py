@@ -21,6 +21,7 @@ from .fullsystem import full_newton_matrix, full_newton_direction
 from .bruteforce import brute_force_qp
 from .adjoint import adjoint_gradients, center
 from .woodbury import woodbury_direction, schur_direction
-from .spectrum import kkt_dense, jacobi_spectrum, condition_numbers
+from .spectrum import (kkt_dense, jacobi_spectrum, condition_numbers, condest,
+                       condest_path, onenorm_inverse_estimate)
 
 __all__ = [n for n in dir() if not n.startswith("_")]
