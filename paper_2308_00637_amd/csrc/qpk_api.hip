@@ -1302,6 +1302,12 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   h->g_epi_x = grid_cap(n, kBlock, kGridMax);
   if (h->ck_r.on) h->g_rmv = h->ck_r.nchunk == 1 ? h->ck_r.nwork : h->g_epi_r;
   if (h->ck_x.on) h->g_xmv = h->ck_x.nchunk == 1 ? h->ck_x.nwork : h->g_epi_x;
+  if (h->fz.on || pcg_fuses_epilogue(h)) {
+    // the PCG update then sums the x-part of q from partials, 16 entries per
+    // wave: one wave per task (k_cg_update_split)
+    const int64_t tasks = (n + 15) / 16 + (h->N() - n + 63) / 64;
+    h->g_vec = (int)std::min<int64_t>(kGridMax, std::max<int64_t>(h->g_vec, (tasks + 3) / 4));
+  }
   if (k > 0) {
     CHK(upload(h, &h->U, d->U, n * k));
     CHK(upload(h, &h->wd, d->wd, k));

@@ -780,22 +780,34 @@ void k_chunked(ChunkArgs b, RowArgs ra, ColArgs ca) {
   chunked_body<EPI, VK, LPR, KV>(b, ra, ca);
 }
 
-// Sum of the per-chunk partials in chunk order, then the matvec epilogue.
-// Partials of row r in chunk order, eight loads in flight at a time.
+// Sum of the per-chunk partials, then the matvec epilogue.  The chunks are
+// cut into four consecutive groups of ceil(nchunk / 4); each group is summed
+// in chunk order from 0.0 and the four sums are combined as (g0 + g1) +
+// (g2 + g3).  The PCG update sums the x-part of q in exactly this order, one
+// group per quarter of a wave, so q is bitwise the same either way.
+__device__ __forceinline__ int partial_group(int nchunk) { return (nchunk + 3) >> 2; }
+
 __device__ __forceinline__ double sum_partials(const ChunkArgs& b, int r) {
   const double* p = b.partial + r;
   const int64_t st = b.nrows;
-  double y = 0.0;
-  int c = 0;
-  for (; c + 8 <= b.nchunk; c += 8) {
-    double t[8];
+  const int g = partial_group(b.nchunk);
+  double y[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = p[(c + u) * st];
+  for (int s = 0; s < 4; ++s) {
+    const int c1 = min(b.nchunk, (s + 1) * g);
+    double acc = 0.0;
+    int c = s * g;
+    for (; c + 8 <= c1; c += 8) {
+      double t[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) y += t[u];
+      for (int u = 0; u < 8; ++u) t[u] = p[(c + u) * st];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += t[u];
+    }
+    for (; c < c1; ++c) acc += p[c * st];
+    y[s] = acc;
   }
-  for (; c < b.nchunk; ++c) y += p[c * st];
-  return y;
+  return (y[0] + y[1]) + (y[2] + y[3]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_chunk_epilogue_col(ChunkArgs b, ColArgs a) {
@@ -1475,39 +1487,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_finish(CgArgs a) {
 
 // The vector loads of a thread's first element are issued before the
 // partial sums are read, so the two memory latencies overlap.
-// q_i of the PCG product: read from q, or for the x-part summed from the
-// column pass's chunk partials in chunk order with the equality and diagonal
-// terms added exactly as the column epilogue adds them (so q is bitwise the
-// same either way).  Up to 32 partial loads are issued at once.
-__device__ __forceinline__ double cg_q(const CgArgs& a, int i, double pi) {
-  if (!a.qpart || i >= a.n) return a.q[i];
-  const double* p = a.qpart + i;
-  const int64_t st = a.n;
-  double y = 0.0;
-  if (a.nchunk <= 32) {
-    double t[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) t[c] = c < a.nchunk ? p[c * st] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 32; ++c)
-      if (c < a.nchunk) y += t[c];
-  } else {
-    // many partials (the fused pass's row ranges): 32 loads in flight at a
-    // time, summed in range order
-    for (int c0 = 0; c0 < a.nchunk; c0 += 32) {
-      double t[32];
-#pragma unroll
-      for (int c = 0; c < 32; ++c) t[c] = c0 + c < a.nchunk ? p[(c0 + c) * st] : 0.0;
-#pragma unroll
-      for (int c = 0; c < 32; ++c)
-        if (c0 + c < a.nchunk) y += t[c];
-    }
-  }
-  for (int e = 0; e < a.me; ++e) y += a.Cm[static_cast<int64_t>(e) * a.n + i] * a.we[e];
-  y += a.qdiag[i] * pi;
-  return y;
-}
-
 __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
   const int stride = gridDim.x * kBlock;
   int i = blockIdx.x * kBlock + threadIdx.x;
@@ -1517,7 +1496,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     pi = a.p[i];
     ri = a.r[i];
     di = a.jdiag[i];
-    qi = cg_q(a, i, pi);
+    qi = a.q[i];
   }
   if (a.fl[F_DONE]) return;
   const int k = a.fl[F_CNT];
@@ -1553,8 +1532,114 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
       pi = a.p[j];
       ri = a.r[j];
       di = a.jdiag[j];
-      qi = cg_q(a, j, pi);
+      qi = a.q[j];
     }
+  }
+  rzn = block_sum(rzn);
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) {
+    a.part[(((k + 1) & 1) ? P_RZ1 : P_RZ0) * kGridMax + blockIdx.x] = rzn;
+    a.part[P_RR * kGridMax + blockIdx.x] = rr;
+  }
+}
+
+// k_cg_update when the x-part of q comes from per-chunk (or per-range)
+// partials: each wave takes 16 entries of the x-part, a quarter of the wave
+// per chunk group, so every lane has at most ceil(nchunk / 4) loads to wait
+// for, all in flight together, and the x-part is spread over the whole grid
+// instead of the first blocks.  The groups' sums meet by two lane exchanges,
+// in the order sum_partials uses.  The rest of K v (the lam-part) is read
+// from q, 64 entries per wave.  Every wave's first task is loaded before the
+// scalar sums are read, as in k_cg_update.
+struct UpdTask {
+  int i;
+  bool own;          // this lane updates entry i
+  double xi, pi, ri, di, y;
+};
+
+__device__ __forceinline__ UpdTask upd_load(const CgArgs& a, int t, int xw, int lane) {
+  UpdTask u;
+  u.xi = u.pi = u.ri = 0.0;
+  u.di = 1.0;
+  u.y = 0.0;
+  if (t < xw) {
+    u.i = t * 16 + (lane & 15);
+    u.own = lane < 16 && u.i < a.n;
+    if (u.i < a.n) {
+      const int g = partial_group(a.nchunk);
+      const int c0 = (lane >> 4) * g, c1 = min(a.nchunk, c0 + g);
+      const double* p = a.qpart + u.i;
+      const int64_t st = a.n;
+      for (int cb = c0; cb < c1; cb += 32) {
+        double v[32];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) v[c] = cb + c < c1 ? p[(cb + c) * st] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+          if (cb + c < c1) u.y += v[c];
+      }
+    }
+  } else {
+    u.i = a.n + (t - xw) * 64 + lane;
+    u.own = u.i < a.N;
+    if (u.own) u.y = a.q[u.i];
+  }
+  if (u.own) {
+    u.xi = a.x[u.i];
+    u.pi = a.p[u.i];
+    u.ri = a.r[u.i];
+    u.di = a.jdiag[u.i];
+  }
+  return u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_update_split(CgArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * (kBlock / 64);
+  const int xw = (a.n + 15) >> 4;
+  const int tasks = xw + (a.N - a.n + 63) / 64;
+  int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  UpdTask u = upd_load(a, t, xw, lane);
+  if (a.fl[F_DONE]) return;
+  const int k = a.fl[F_CNT];
+  const double* P = a.part;
+  double pqr, pqx, rz;
+  sum3_bcast(P + P_DOT_R * kGridMax, a.g_r, P + P_DOT_X * kGridMax, a.g_x,
+             P + ((k & 1) ? P_RZ1 : P_RZ0) * kGridMax, a.g_vec, pqr, pqx, rz);
+  double pq = pqr + pqx;
+  if (a.has_ts)
+    for (int e = 0; e < a.me; ++e) pq += P[P_DOT_TS * kGridMax + e];
+  if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.fl[F_STATUS] = (isfinite(pq) && isfinite(rz)) ? QP_ERR_NOT_SPD_CODE : QP_ERR_NUMERIC_CODE;
+      a.fl[F_ITERS] = k;
+      a.fl[F_DONE] = 1;
+    }
+    return;
+  }
+  const double alpha = rz / pq;
+  if (a.coef && blockIdx.x == 0 && threadIdx.x == 0) a.coef[2 * k] = alpha;
+  double rzn = 0.0, rr = 0.0;
+  for (; t < tasks; t += nw) {
+    double qi = u.y;
+    if (t < xw) {
+      const double y01 = qi + __shfl_xor(qi, 16, 64);
+      qi = y01 + __shfl_xor(y01, 32, 64);
+      if (u.own) {
+        for (int e = 0; e < a.me; ++e) qi += a.Cm[static_cast<int64_t>(e) * a.n + u.i] * a.we[e];
+        qi += a.qdiag[u.i] * u.pi;
+      }
+    }
+    if (u.own) {
+      a.x[u.i] = u.xi + alpha * u.pi;
+      const double r = u.ri - alpha * qi;
+      const double z = r / u.di;
+      a.r[u.i] = r;
+      a.z[u.i] = z;
+      rzn += r * z;
+      rr += r * r;
+    }
+    if (t + nw < tasks) u = upd_load(a, t + nw, xw, lane);
   }
   rzn = block_sum(rzn);
   rr = block_sum(rr);
@@ -1927,6 +2012,7 @@ hipError_t launch_cg_init(const CgArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_cg_update(const CgArgs& a, hipStream_t st, const KEvents* ev) {
+  if (a.qpart) return launch_ev(ev, k_cg_update_split, dim3(a.g_vec), dim3(kBlock), 0, st, a);
   return launch_ev(ev, k_cg_update, dim3(a.g_vec), dim3(kBlock), 0, st, a);
 }
 hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st, const KEvents* ev) {
