@@ -21,6 +21,7 @@ from .fullsystem import full_newton_matrix, full_newton_direction
 from .bruteforce import brute_force_qp
 from .adjoint import adjoint_gradients, center
 from .woodbury import woodbury_direction, schur_direction
+from .mehrotra import solve_mpc, target_residuals, complementarity, pair_count
 from .spectrum import (kkt_dense, jacobi_spectrum, condition_numbers, condest,
                        condest_path, onenorm_inverse_estimate)
 
