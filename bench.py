@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--workload", default="rt_full",
                     choices=["rt_full", "rt_small", "svm_full", "svm_rbf", "qn_rt", "tiny_dense"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16", "fp32x64", "bf16x64"])
+    ap.add_argument("--mu-rule", default="paper", choices=["paper", "mehrotra"],
+                    help="the barrier parameter's rule: Algorithm 1's (default) or Mehrotra's "
+                         "predictor-corrector (two PCG solves per IPM iteration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle PCG iterations for the CPU baseline (0: pick ~15 s)")
@@ -415,7 +418,7 @@ def main():
         torch.cuda.synchronize()
         t_create = time.perf_counter() - t0
         print(f"[bench] qp_create {t_create:.2f}s", file=sys.stderr, flush=True)
-        opts = default_ipm_options()
+        opts = default_ipm_options(mu_rule=1 if args.mu_rule == "mehrotra" else 0)
         for w in range(args.warmup):
             out = qp.solve(opts, want_state=False)
             inf = out["info"]
@@ -489,7 +492,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else f"{args.precision} matvec / f64",
         "data": "synthetic",
-        "config": {"workload": spec.name, "n": spec.n, "m": spec.m, "me": spec.me,
+        "config": {"workload": spec.name, "mu_rule": args.mu_rule, "n": spec.n, "m": spec.m, "me": spec.me,
                    "N_kkt": spec.n + spec.me + spec.m, "precision": args.precision,
                    "pcg_tol": 1e-7, "pcg_maxit": 5000},
         "ipm_solve_time_s": solve_s / args.steps,

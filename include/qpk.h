@@ -181,7 +181,27 @@ typedef struct {
                               * the pcg tolerance and cap), for this log only (the iterate
                               * does not use it; its time counts in time_ms, not in
                               * pcg_time_ms or total_cg_iters).  Float64 handles */
+  /* The barrier parameter's rule.  QP_MU_PAPER (0, the default): Algorithm 1,
+   * mu divided by mu_div whenever the stacked residual is below mu, stop once
+   * mu < mu_tol.  QP_MU_MEHROTRA (1): the predictor-corrector rule that
+   * Sections 5.2 and 7 leave to future work (Mehrotra 1992), on the same
+   * Newton system eq. (9): mu = lam^T s / N_c (N_c finite sides), also the
+   * equality rows' penalty; a predictor solve for complementarity target 0,
+   * its largest steps to the boundary (gamma = 1), sigma = min(1, (mu_aff /
+   * mu)^3) with mu_aff the complementarity average after those steps; a
+   * corrector solve for target max(sigma mu, mu_tol / (2 mu_div)) with the
+   * predictor's dlam * ds added to each complementarity residual; the step
+   * with gamma.  Two PCG solves per iteration (total_cg_iters counts both).
+   * It stops when mu and the primal and dual residuals (target 0) are below
+   * mu_tol / mu_div; mu0 and warm_start's mu are not used.  With no
+   * inequality constraints the paper's rule runs.  log_rnorm, log_compl and
+   * ipm_info's residuals are those of the new point for its own mu (target
+   * and penalty), as under the paper's rule. */
+  int32_t mu_rule;
+  double* log_sigma;         /* QP_MU_MEHROTRA: sigma of each iteration, or NULL */
 } ipm_options;
+
+enum { QP_MU_PAPER = 0, QP_MU_MEHROTRA = 1 };
 
 typedef enum { QP_IPM_CONVERGED = 0, QP_IPM_MAX_ITER = 1 } qp_ipm_result;
 
@@ -304,7 +324,8 @@ qp_status qp_backward(qp_handle h, const double* grad_x, double* grad_c,
  * `workgroups` (<= 0: 512) workgroups of 1024 threads take instances from a
  * queue, largest first, and each solves its instances start to finish (same
  * steps, readings and defaults as ipm_solve; per-iteration logs are not
- * kept; of o->pcg only tol and maxit are read: always Jacobi, no spectrum).
+ * kept; of o->pcg only tol and maxit are read: always Jacobi, no spectrum;
+ * mu_rule must be QP_MU_PAPER, else QP_ERR_UNSUPPORTED).
  * infos: HOST array of `count`, each time_ms is the whole launch.
  * Returns QP_ERR_NOT_SPD / QP_ERR_NUMERIC if an instance stopped on one
  * (the others are still solved).  qp_batch_get_solution copies instance i's
@@ -332,7 +353,8 @@ const char* qp_batch_last_error(qp_batch b);
  * lam, s (2m + 2n, layouts as for a handle with me = 0) are DEVICE pointers,
  * each may be NULL; info (HOST) must not be NULL, and filling it synchronises
  * the stream (hipStream_t, NULL = default).  Of o only the IPM constants and
- * pcg.tol / pcg.maxit are read; warm_start is not supported.  Every call on
+ * pcg.tol / pcg.maxit are read; warm_start and QP_MU_MEHROTRA are not
+ * supported (QP_ERR_UNSUPPORTED).  Every call on
  * one GPU uses that GPU's array: calls that overlap on a GPU (other host
  * threads, other streams) race.  Error messages: qp_batch_last_error(NULL). */
 qp_status ipm_solve_dense_noalloc(int64_t n, int64_t m, const double* H, const double* c,

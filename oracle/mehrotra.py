@@ -27,7 +27,7 @@ few 1e-6, D = s / lam reaches 1e-17 and the doubly augmented matrix is no
 longer positive definite in float64.
 
 It stops when, at the new point, mu and the primal and dual residuals
-(complementarity target 0, penalty mu) are both below mu_tol / mu_div: the
+(with that mu as the equality rows' penalty) are both below mu_tol / mu_div: the
 accuracy at which the paper's rule stops (its last point has ||r(mu)|| < mu
 with mu = mu_tol / mu_div).  Without inequality constraints there is no
 complementarity to measure and the paper's rule is used.
@@ -109,11 +109,11 @@ def solve_mpc(prob: Problem, opts: IPMOptions = IPMOptions(), direction=None,
         ax, al = step_lengths(st, d, opts.gamma)
         st = take_step(st, d, ax, al)
         mu_new = complementarity(st) / nc
-        res0 = target_residuals(prob, st, mu_new, 0.0)
-        pd = primal_dual_norm(res0)
+        res_new = residuals(prob, st, mu_new)
+        pd = primal_dual_norm(res_new)
         log.append(dict(it=it, mu=mu, sigma=sigma, tau=tau, alpha_x_aff=ax_a, alpha_lam_aff=al_a,
                         alpha_x=ax, alpha_lam=al, mu_new=mu_new, pd=pd,
-                        rnorm=stacked_norm(res0)))
+                        rnorm=stacked_norm(res_new)))
         mu = mu_new
         if mu < tol and pd < tol:
             return IPMResult(st, mu, "converged", it, objective(prob, st.x), log)

@@ -43,6 +43,10 @@ struct qp_handle_s {
   // iterate
   double *x = nullptr, *lam = nullptr, *s = nullptr;
   double mu = 1.0;
+  // Mehrotra rule: the residuals' complementarity target while tau_on (else mu)
+  double tau = 0.0;
+  bool tau_on = false;
+  double *dlam_aff = nullptr, *ds_aff = nullptr;   // the predictor's direction
   bool solved = false;
   bool res_valid = false, sys_valid = false;
   // work
@@ -228,6 +232,7 @@ static RowArgs row_args(qp_handle h, bool lo) {
   a.val = lo ? h->rp_lo : (const void*)h->rp_val;
   a.w = h->pw; a.d = h->pd; a.u = h->u; a.lA = h->lA; a.uA = h->uA;
   a.lam = h->lam; a.s = h->s; a.mu = h->mu; a.res = h->res;
+  a.tau = h->tau_on ? h->tau : h->mu;
   return a;
 }
 
@@ -241,6 +246,7 @@ static ColArgs col_args(qp_handle h, bool lo) {
   a.g = h->g; a.Cm = h->Cm; a.qdiag = h->qdiag;
   a.c = h->c_eff; a.h0 = h->h0; a.lam = h->lam; a.s = h->s; a.lx = h->lx; a.ux = h->ux;
   a.mu = h->mu; a.diagH = h->diagH; a.wd = h->wd; a.w = h->pw;
+  a.tau = h->tau_on ? h->tau : h->mu;
   return a;
 }
 
@@ -1605,6 +1611,116 @@ qp_status qp_take_step(qp_handle h, const double* dx, const double* dlam, const 
   return QP_OK;
 }
 
+// Mehrotra rule: lam^T s over the inequality pairs into sc[S_MU_CUR] and the
+// count of pairs into sc[S_NPAIRS], or, with the predictor's direction,
+// its value after the affine steps (alphas in sc) into sc[S_MU_AFF]; read back.
+static qp_status mpc_sums(qp_handle h, const double* dlam, const double* ds) {
+  VecArgs v = vec_args(h);
+  const int grid = grid_cap(h->ns(), kBlock, kGridMax);
+  double* P = h->part;
+  HIPCHK(launch_compl(v, dlam, ds, P + P_CMP0 * kGridMax, P + P_CMP1 * kGridMax,
+                      P + P_CMP2 * kGridMax, grid, h->st));
+  HIPCHK(launch_finish_sum(P + P_CMP0 * kGridMax, grid, h->sc + S_MU_CUR, h->st));
+  HIPCHK(launch_finish_sum(P + (dlam ? P_CMP1 : P_CMP2) * kGridMax, grid,
+                           h->sc + (dlam ? S_MU_AFF : S_NPAIRS), h->st));
+  return read_back(h);
+}
+
+// Algorithm 1 with the Mehrotra predictor-corrector rule (ipm_options.mu_rule):
+// per iteration a predictor and a corrector solve of eq. (9) with one K.
+static qp_status run_mpc(qp_handle h, const ipm_options& opt, const pcg_options& po, double np,
+                         ipm_info* info, double* pcg_ms, bool* converged, int* iters) {
+  const double tol = opt.mu_tol / opt.mu_div;
+  if (!h->dlam_aff) CHK(dalloc_t(h, &h->dlam_aff, h->nlam()));
+  if (!h->ds_aff) CHK(dalloc_t(h, &h->ds_aff, h->ns()));
+  const int gv = grid_cap(h->ns(), kBlock, kGridMax);
+  double mu = h->hsc[S_MU_CUR] / np;
+  h->tau_on = true;
+  int it = 0;
+  *converged = false;
+  for (it = 1; it <= opt.max_iter; ++it) {
+    // predictor: complementarity target 0, penalty mu
+    h->mu = mu;
+    h->tau = 0.0;
+    h->res_valid = h->sys_valid = false;
+    CHK(prepare(h));
+    auto tp = std::chrono::steady_clock::now();
+    pcg_info pa{};
+    CHK(run_pcg(h, h->rhs, h->dir, po, &pa));
+    *pcg_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
+    CHK(run_recover(h, 1.0));
+    HIPCHK(launch_copy(h->dir + h->n, h->dlam_aff, h->nlam(), 1.0, h->st));
+    HIPCHK(launch_copy(h->ds_w, h->ds_aff, h->ns(), 1.0, h->st));
+    CHK(mpc_sums(h, h->dlam_aff, h->ds_aff));
+    const double mu_aff = h->hsc[S_MU_AFF] / np;
+    const double sigma = std::min(1.0, std::pow(mu_aff / mu, 3.0));
+    // corrector: target max(sigma mu, tol / 2), second-order term, same K
+    h->tau = std::max(sigma * mu, 0.5 * tol);
+    CHK(run_residuals(h));
+    VecArgs v = vec_args(h);
+    HIPCHK(launch_second_order(v, h->res, h->dlam_aff, h->ds_aff, gv, h->st));
+    CHK(run_system(h));
+    tp = std::chrono::steady_clock::now();
+    pcg_info pc{};
+    CHK(run_pcg(h, h->rhs, h->dir, po, &pc));
+    *pcg_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
+    for (const pcg_info* pi : {&pa, &pc}) {
+      info->total_cg_iters += pi->iterations;
+      if (!pi->converged) info->cg_maxiter_hits++;
+      if (pi->escalated) info->cg_escalations++;
+    }
+    CHK(run_recover(h, opt.gamma));
+    v = vec_args(h);
+    HIPCHK(launch_update(v, h->dir, h->dir + h->n, h->ds_w, h->sc + S_ALPHA_X, 0.0, 0.0,
+                         grid_cap(h->nlam(), kBlock, kGridMax), h->st));
+    h->res_valid = h->sys_valid = false;
+    // the new point: mu, and its residuals for that mu (target and penalty),
+    // as Algorithm 1 measures them; the stop test uses their primal and dual part
+    CHK(mpc_sums(h, nullptr, nullptr));
+    const double mu_new = h->hsc[S_MU_CUR] / np;
+    h->mu = mu_new;
+    h->tau = mu_new;
+    CHK(run_residuals(h));
+    CHK(read_back(h));
+    const double nr = h->hsc[S_NORM], co = h->hsc[S_COMPL];
+    if (!std::isfinite(nr) || !std::isfinite(mu_new)) {
+      h->tau_on = false;
+      h->err = "residual norm is not finite";
+      return QP_ERR_NUMERIC;
+    }
+    const double pd = std::sqrt(std::max(0.0, nr * nr - co * co));
+    const int li = it - 1;
+    if (li < opt.log_capacity) {
+      if (opt.log_mu) opt.log_mu[li] = mu;
+      if (opt.log_sigma) opt.log_sigma[li] = sigma;
+      if (opt.log_rnorm) opt.log_rnorm[li] = nr;
+      if (opt.log_primal) opt.log_primal[li] = h->hsc[S_PRIMAL];
+      if (opt.log_dual) opt.log_dual[li] = h->hsc[S_DUAL];
+      if (opt.log_compl) opt.log_compl[li] = co;
+      if (opt.log_alpha_x) opt.log_alpha_x[li] = h->hsc[S_ALPHA_X];
+      if (opt.log_alpha_lam) opt.log_alpha_lam[li] = h->hsc[S_ALPHA_L];
+      if (opt.log_cg_iters) opt.log_cg_iters[li] = pa.iterations + pc.iterations;
+      if (opt.log_cg_relres) opt.log_cg_relres[li] = pc.rel_residual;
+      if (opt.log_kappa)
+        opt.log_kappa[li] = pa.lambda_min > 0.0 ? pa.lambda_max / pa.lambda_min : 0.0;
+    }
+    info->rnorm = nr;
+    info->primal = h->hsc[S_PRIMAL];
+    info->dual = h->hsc[S_DUAL];
+    info->compl_ = co;
+    mu = mu_new;
+    if (mu < tol && pd < tol) {
+      *converged = true;
+      break;
+    }
+  }
+  h->tau_on = false;
+  h->mu = mu;
+  h->res_valid = h->sys_valid = false;
+  *iters = *converged ? it : opt.max_iter;
+  return QP_OK;
+}
+
 qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, double* s,
                     ipm_info* info) {
   if (!h || !info) return QP_ERR_ARG;
@@ -1613,7 +1729,7 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
   if (o) opt = *o;
   const pcg_options po = pcg_opts_or_default(&opt.pcg);
   if (!(opt.gamma > 0.0 && opt.gamma < 1.0) || !(opt.mu0 > 0.0) || !(opt.mu_div > 1.0) ||
-      opt.max_iter < 1) {
+      opt.max_iter < 1 || (opt.mu_rule != QP_MU_PAPER && opt.mu_rule != QP_MU_MEHROTRA)) {
     h->err = "invalid ipm_options";
     return QP_ERR_ARG;
   }
@@ -1626,7 +1742,18 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
   h->solved = false;
   int it = 0;
   bool converged = false;
-  for (it = 1; it <= opt.max_iter; ++it) {
+  bool mpc_done = false;
+  int mpc_iters = 0;
+  if (opt.mu_rule == QP_MU_MEHROTRA) {
+    CHK(mpc_sums(h, nullptr, nullptr));
+    const double np = h->hsc[S_NPAIRS];
+    if (np > 0.0) {
+      // with no inequality pairs there is no complementarity: the paper's rule
+      CHK(run_mpc(h, opt, po, np, info, &pcg_ms, &converged, &mpc_iters));
+      mpc_done = true;
+    }
+  }
+  for (it = 1; !mpc_done && it <= opt.max_iter; ++it) {
     CHK(prepare(h));
     const auto tp = std::chrono::steady_clock::now();
     pcg_info pi{};
@@ -1686,7 +1813,8 @@ qp_status ipm_solve(qp_handle h, const ipm_options* o, double* x, double* lam, d
       h->res_valid = h->sys_valid = false;
     }
   }
-  info->iterations = converged ? it : opt.max_iter;
+  if (mpc_done) info->iterations = mpc_iters;
+  else info->iterations = converged ? it : opt.max_iter;
   info->result = converged ? QP_IPM_CONVERGED : QP_IPM_MAX_ITER;
   info->mu_final = h->mu;
   CHK(run_objective(h, &info->objective));

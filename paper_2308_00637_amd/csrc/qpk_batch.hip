@@ -804,6 +804,7 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
   qp_default_ipm_options(&opt);
   if (o) opt = *o;
   if (opt.warm_start) { b->err = "batched solves always start from the default point"; return QP_ERR_UNSUPPORTED; }
+  if (opt.mu_rule != QP_MU_PAPER) { b->err = "batched solves run the paper's mu rule"; return QP_ERR_UNSUPPORTED; }
   BOpts bo{};
   bo.gamma = opt.gamma; bo.mu0 = opt.mu0; bo.mu_tol = opt.mu_tol; bo.mu_div = opt.mu_div;
   bo.max_iter = opt.max_iter;
@@ -912,6 +913,10 @@ qp_status ipm_solve_dense_noalloc(int64_t n, int64_t m, const double* H, const d
   if (o) opt = *o;
   if (opt.warm_start) {
     g_batch_error = "the allocation-free solve always starts from the default point";
+    return QP_ERR_UNSUPPORTED;
+  }
+  if (opt.mu_rule != QP_MU_PAPER) {
+    g_batch_error = "the allocation-free solve runs the paper's mu rule";
     return QP_ERR_UNSUPPORTED;
   }
   BOpts bo{};

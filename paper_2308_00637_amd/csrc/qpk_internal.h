@@ -62,6 +62,7 @@ struct RowArgs {
   const double* lam;
   const double* s;
   double mu;
+  double tau;                // complementarity target of R_RESID (mu under the paper's rule)
   const double* res;         // residual stack (R_RECOVER reads r_lA, r_uA)
   double* resw;              // residual stack output (R_RESID)
   const double* dlam;        // R_RECOVER: direction lam (iterate layout)
@@ -109,6 +110,7 @@ struct ColArgs {
   const double* lx;
   const double* ux;
   double mu;
+  double tau;                // complementarity target of X_RESID (mu under the paper's rule)
   double* res;
   const double* res_in;
   double* rhs;
@@ -230,13 +232,15 @@ namespace qpk {
 enum PartRegion : int {
   P_DOT_R = 0, P_DOT_X, P_DOT_TS, P_RZ0, P_RZ1, P_RR, P_RR0,
   P_NR_PRIMAL, P_NR_COMPL, P_NX_DUAL, P_NX_PRIMAL, P_NX_COMPL, P_NTS_RE,
-  P_MIN_S_R, P_MIN_L_R, P_MIN_S_X, P_MIN_L_X, P_OBJ, P_CHK, P_COUNT
+  P_MIN_S_R, P_MIN_L_R, P_MIN_S_X, P_MIN_L_X, P_OBJ, P_CHK, P_CMP0, P_CMP1, P_CMP2, P_COUNT
 };
 
 // Device scalars (double) and flags (int).
 enum Scalar : int {
   S_ALPHA_X = 0, S_ALPHA_L, S_NORM, S_PRIMAL, S_DUAL, S_COMPL, S_RHSNORM,
-  S_OBJ, S_RELRES, S_RECUR, S_COUNT
+  S_OBJ, S_RELRES, S_RECUR,
+  S_MU_CUR, S_MU_AFF, S_NPAIRS,   // Mehrotra rule: lam^T s, its value after the affine steps, N_c
+  S_COUNT
 };
 enum Flag : int { F_DONE = 0, F_CNT, F_STATUS, F_ITERS, F_BAD, F_FUSEFAIL, F_COUNT };
 
@@ -341,5 +345,13 @@ hipError_t launch_sqdiff(const double* a, const double* b, int64_t n, double* pa
                          hipStream_t st);
 hipError_t launch_ratio_given(const VecArgs& a, const double* dlam, const double* ds, int grid,
                               hipStream_t st);
+// Mehrotra rule: per-block sums of lam^T s (part0), of (lam + al dlam)^T
+// (s + ax ds) with the ratio test's alphas from sc (part1, when dlam is set)
+// and of the count of finite sides (part2); and the corrector's
+// complementarity residuals r_c += dlam * ds.
+hipError_t launch_compl(const VecArgs& a, const double* dlam, const double* ds, double* part0,
+                        double* part1, double* part2, int grid, hipStream_t st);
+hipError_t launch_second_order(const VecArgs& a, double* res, const double* dlam, const double* ds,
+                               int grid, hipStream_t st);
 
 }  // namespace qpk

@@ -215,8 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_rowpass(RowArgs a) {
       const double sl = a.s[i], su = a.s[m + i];
       const double rl = hl ? td - sl - a.lA[i] : 0.0;
       const double ru = hu ? -td - su + a.uA[i] : 0.0;
-      const double c1 = hl ? ll * sl - a.mu : 0.0;
-      const double c2 = hu ? lu * su - a.mu : 0.0;
+      const double c1 = hl ? ll * sl - a.tau : 0.0;
+      const double c2 = hu ? lu * su - a.tau : 0.0;
       a.resw[o.rlA + i] = rl;
       a.resw[o.ruA + i] = ru;
       a.resw[o.rc1 + i] = c1;
@@ -406,8 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_colpass(ColArgs a) {
       y += -llx + lux;
       const double rlx = hl ? xj - slx - a.lx[j] : 0.0;
       const double rux = hu ? -xj - sux + a.ux[j] : 0.0;
-      const double c3 = hl ? llx * slx - a.mu : 0.0;
-      const double c4 = hu ? lux * sux - a.mu : 0.0;
+      const double c3 = hl ? llx * slx - a.tau : 0.0;
+      const double c4 = hu ? lux * sux - a.tau : 0.0;
       a.res[o.rH + j] = y;
       a.res[o.rlx + j] = rlx;
       a.res[o.rux + j] = rux;
@@ -1716,6 +1716,50 @@ __global__ void k_cg_rearm(int* fl) {
   }
 }
 
+// Mehrotra predictor-corrector rule (an alternative to Algorithm 1's mu
+// update): the complementarity sums over the inequality pairs, in the slack
+// layout q = [lA (m) | uA (m) | lx (n) | ux (n)] with lam[me + q] the
+// multiplier of slack q.  Absent sides hold zeros in lam, s and the
+// direction, so they add nothing to the sums; they are left out of the count.
+__global__ __launch_bounds__(kBlock) void k_compl(VecArgs a, const double* dlam, const double* ds,
+                                                 double* part0, double* part1, double* part2) {
+  const int n = a.n, m = a.m, me = a.me;
+  const int ns = 2 * (m + n);
+  const double ax = dlam ? a.sc[S_ALPHA_X] : 0.0, al = dlam ? a.sc[S_ALPHA_L] : 0.0;
+  double c0 = 0.0, c1 = 0.0, cnt = 0.0;
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < ns; q += gridDim.x * kBlock) {
+    const double l = a.lam[me + q], sq = a.s[q];
+    c0 += l * sq;
+    if (dlam) c1 += (l + al * dlam[me + q]) * (sq + ax * ds[q]);
+    bool present;
+    if (q < m) present = has_lo(a.lA[q]);
+    else if (q < 2 * m) present = has_hi(a.uA[q - m]);
+    else if (q < 2 * m + n) present = has_lo(a.lx[q - 2 * m]);
+    else present = has_hi(a.ux[q - 2 * m - n]);
+    cnt += present ? 1.0 : 0.0;
+  }
+  c0 = block_sum(c0);
+  c1 = block_sum(c1);
+  cnt = block_sum(cnt);
+  if (threadIdx.x == 0) {
+    part0[blockIdx.x] = c0;
+    part1[blockIdx.x] = c1;
+    part2[blockIdx.x] = cnt;
+  }
+}
+
+// The corrector's right side: each complementarity residual (r_c1..r_c4,
+// consecutive in the stack, in the slack layout) gains the predictor's
+// dlam * ds, so the complementarity rows read lam ds + s dlam = tau - lam s -
+// dlam^a ds^a.
+__global__ __launch_bounds__(kBlock) void k_second_order(VecArgs a, double* res, const double* dlam,
+                                                        const double* ds) {
+  const ResOff o(a.n, a.m, a.me);
+  const int ns = 2 * (a.m + a.n);
+  for (int q = blockIdx.x * kBlock + threadIdx.x; q < ns; q += gridDim.x * kBlock)
+    res[o.rc1 + q] += dlam[a.me + q] * ds[q];
+}
+
 // Squared distance partials (true residual ||rhs - K x||^2).
 __global__ __launch_bounds__(kBlock) void k_sqdiff(const double* a, const double* b, int64_t n,
                                                   double* part) {
@@ -2014,6 +2058,16 @@ hipError_t launch_cg_init(const CgArgs& a, hipStream_t st) {
 hipError_t launch_cg_update(const CgArgs& a, hipStream_t st, const KEvents* ev) {
   if (a.qpart) return launch_ev(ev, k_cg_update_split, dim3(a.g_vec), dim3(kBlock), 0, st, a);
   return launch_ev(ev, k_cg_update, dim3(a.g_vec), dim3(kBlock), 0, st, a);
+}
+hipError_t launch_compl(const VecArgs& a, const double* dlam, const double* ds, double* part0,
+                        double* part1, double* part2, int grid, hipStream_t st) {
+  k_compl<<<grid, kBlock, 0, st>>>(a, dlam, ds, part0, part1, part2);
+  return hipGetLastError();
+}
+hipError_t launch_second_order(const VecArgs& a, double* res, const double* dlam, const double* ds,
+                               int grid, hipStream_t st) {
+  k_second_order<<<grid, kBlock, 0, st>>>(a, res, dlam, ds);
+  return hipGetLastError();
 }
 hipError_t launch_cg_pupdate(const CgArgs& a, hipStream_t st, const KEvents* ev) {
   return launch_ev(ev, k_cg_pupdate, dim3(a.g_vec), dim3(kBlock), 0, st, a);

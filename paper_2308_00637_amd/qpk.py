@@ -25,6 +25,8 @@ QP_ERR_NOT_SPD = -4
 QP_ERR_NUMERIC = -5
 QP_ERR_STATE = -6
 QP_ERR_UNSUPPORTED = -7
+QP_MU_PAPER = 0
+QP_MU_MEHROTRA = 1
 
 H_DENSE, H_LOWRANK, H_PTWP = 0, 1, 2
 A_NONE, A_DENSE, A_CSR = 0, 1, 2
@@ -65,7 +67,7 @@ class IpmOptions(C.Structure):
         ("log_mu", _dp), ("log_rnorm", _dp), ("log_primal", _dp), ("log_dual", _dp),
         ("log_compl", _dp), ("log_alpha_x", _dp), ("log_alpha_lam", _dp),
         ("log_cg_iters", _i32p), ("log_cg_relres", _dp), ("log_kappa", _dp),
-        ("log_kappa_plain", _dp),
+        ("log_kappa_plain", _dp), ("mu_rule", C.c_int32), ("log_sigma", _dp),
     ]
 
 
@@ -357,7 +359,7 @@ class QP:
         if log:
             cap = max(int(opts.max_iter), 1)
             keys = ["mu", "rnorm", "primal", "dual", "compl", "alpha_x", "alpha_lam", "cg_relres",
-                    "kappa"] + (["kappa_plain"] if log_kappa_plain else [])
+                    "kappa", "sigma"] + (["kappa_plain"] if log_kappa_plain else [])
             logs = {k: np.zeros(cap) for k in keys}
             logs["cg_iters"] = np.zeros(cap, dtype=np.int32)
             opts.log_capacity = cap
