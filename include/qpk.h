@@ -334,6 +334,20 @@ typedef struct qp_batch_s* qp_batch;
 qp_status qp_batch_create(const qp_desc* descs, int32_t count, void* stream, qp_batch* out);
 void qp_batch_destroy(qp_batch b);
 qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, ipm_info* infos);
+/* Teams of workgroups for large instances.  team_size (HOST, one entry per
+ * instance, each a power of two from 1 to 64; NULL: all 1) sets how many
+ * workgroups solve each instance together: its rows, columns and vector
+ * entries are spread over the team, whose phases meet at device-wide team
+ * barriers and whose reductions combine the members' partials in rank order
+ * (so results differ from a team of one by rounding only).  With any size
+ * above 1, ipm_solve_batch makes one cooperative launch of at most the
+ * co-resident workgroups (and at most `workgroups` when positive): each team
+ * size gets its own queue of instances and a number of teams in proportion to
+ * its instances' work.  A team whose members cannot all be resident is
+ * reported as QP_ERR_HIP rather than waited for.  qp_batch_launch_shape
+ * returns the last launch's workgroups and teams (HOST outs, may be NULL). */
+qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size);
+qp_status qp_batch_launch_shape(qp_batch b, int32_t* workgroups, int32_t* teams);
 qp_status qp_batch_get_solution(qp_batch b, int32_t i, double* x, double* lam, double* s);
 const char* qp_batch_last_error(qp_batch b);
 

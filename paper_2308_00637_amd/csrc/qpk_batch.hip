@@ -26,11 +26,15 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <type_traits>
+#include <functional>
 
 namespace qpk {
 
 constexpr int kBB = 1024;            // threads per workgroup
 constexpr int kBW = kBB / 64;        // waves per workgroup
+constexpr int kTeamMax = 64;         // most workgroups in one team
+constexpr int kRedSlots = 4;         // rotating slots of a team's reductions
 
 struct BInst {
   int32_t n, m, k, hkind;            // hkind: 0 dense H, 1 low rank
@@ -70,6 +74,35 @@ struct BResult {
   int64_t total_cg;
 };
 
+// A team's state in device memory: its barrier's arrival count (monotonic
+// over the launch), the instance it is on, and each member's partials of the
+// team's reductions, in rotating slots.
+struct TeamSync {
+  unsigned long long bar;
+  int32_t cur, pad;
+  double red[kRedSlots][kTeamMax][4];
+};
+
+// How a team launch is organised: workgroup w belongs to team team_of[w],
+// whose members are workgroups first[t] .. first[t] + size[t] - 1; team t
+// takes instances from queue queue[t], i.e. qorder[qstart[q] + i] for the
+// i it draws from the counter qnext[q] (i < qcount[q]).  A wait at a team
+// barrier gives up after spin_max polls and sets *abort (every later wait
+// then returns at once; the results of that launch are invalid).
+struct TeamPlan {
+  const int32_t* team_of;
+  const int32_t* first;
+  const int32_t* size;
+  const int32_t* queue;
+  const int32_t* qstart;
+  const int32_t* qcount;
+  int32_t* qnext;
+  const int32_t* qorder;
+  TeamSync* sync;
+  int32_t* abort;
+  int32_t spin_max;
+};
+
 template <typename T>
 struct BArgs {
   const BInst* inst;
@@ -79,59 +112,132 @@ struct BArgs {
   double* vec;
   BResult* out;
   BOpts o;
+  TeamPlan plan;   // plan.team_of null: every workgroup a team of its own on `order`
 };
 
 __device__ __forceinline__ bool blo(double l) { return l > -INFINITY; }
 __device__ __forceinline__ bool bhi(double u) { return u < INFINITY; }
 
-// Reductions over the workgroup; the result is returned to every thread.
-__device__ __forceinline__ double wg_sum(double v) {
-  __shared__ double sh[kBW];
-  __shared__ double res;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+// The workgroups solving one instance together.  Work is spread over the
+// team's threads (tid, nthr), waves (wave, nwave) and 256-column tiles; the
+// team's phases are separated by team_sync.  A team of one is a workgroup:
+// its barrier is __syncthreads and its reductions stay in LDS.
+struct Team {
+  int G, r;
+  TeamSync* ts;
+  int32_t* abort;
+  int32_t spin_max;
+  unsigned long long gen;   // barriers passed
+  int slot;                 // next reduction slot
+  __device__ int tid() const { return r * kBB + static_cast<int>(threadIdx.x); }
+  __device__ int nthr() const { return G * kBB; }
+  __device__ int wave() const { return r * kBW + static_cast<int>(threadIdx.x >> 6); }
+  __device__ int nwave() const { return G * kBW; }
+};
+
+// Team barrier: every member's writes so far are visible to every member
+// after it.  Thread 0 of each member releases its workgroup's writes at
+// device scope, counts its arrival and waits for the count of this barrier,
+// then acquires; the workgroup's own barrier brackets it.
+__device__ __noinline__ void team_sync(Team& t) {
   __syncthreads();
+  if (t.G == 1) return;
+  ++t.gen;
   if (threadIdx.x == 0) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < kBW; ++i) s += sh[i];
-    res = s;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(&t.ts->bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long target = t.gen * static_cast<unsigned long long>(t.G);
+    int spin = 0;
+    while (__hip_atomic_load(&t.ts->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(t.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (++spin >= t.spin_max) {
+        __hip_atomic_store(t.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  const double r = res;
-  __syncthreads();
-  return r;
 }
 
-__device__ __forceinline__ double wg_min(double v) {
-  __shared__ double sh[kBW];
-  __shared__ double res;
+// Sums (MIN: minima) over the team of NV values per thread, the same bits on
+// every thread of every member: each workgroup reduces by wave shuffles and
+// then its waves in order; with several members their results are combined
+// in rank order through the team's reduction slot.
+template <int NV, bool MIN = false>
+__device__ __forceinline__ void team_reduce(Team& t, double* v) {
+  __shared__ double sh[4][kBW];
+  __shared__ double res[4];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = INFINITY;
+  for (int k = 0; k < NV; ++k) {
 #pragma unroll
-    for (int i = 0; i < kBW; ++i) s = fmin(s, sh[i]);
-    res = s;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double w = __shfl_xor(v[k], o, 64);
+      v[k] = MIN ? fmin(v[k], w) : v[k] + w;
+    }
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v[k];
   }
   __syncthreads();
-  const double r = res;
+  if (threadIdx.x < NV) {
+    double a = MIN ? INFINITY : 0.0;
+#pragma unroll
+    for (int i = 0; i < kBW; ++i) a = MIN ? fmin(a, sh[threadIdx.x][i]) : a + sh[threadIdx.x][i];
+    res[threadIdx.x] = a;
+  }
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = res[k];
+  if (t.G == 1) {
+    __syncthreads();
+    return;
+  }
+  const int slot = t.slot;
+  t.slot = (t.slot + 1) % kRedSlots;
+  if (threadIdx.x < NV) t.ts->red[slot][t.r][threadIdx.x] = res[threadIdx.x];
+  team_sync(t);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double a = MIN ? INFINITY : 0.0;
+    for (int q = 0; q < t.G; ++q) a = MIN ? fmin(a, t.ts->red[slot][q][k]) : a + t.ts->red[slot][q][k];
+    v[k] = a;
+  }
 }
 
-// out[r] = sum_c M[r][c] * v[c] (SQ: M^2), one wave per row.
+__device__ __forceinline__ double team_sum(Team& t, double v) {
+  team_reduce<1>(t, &v);
+  return v;
+}
+
+// Loads in flight per lane in the operator loops below: each batch issues
+// all of its loads before the first product, so a wave waits for one memory
+// latency per batch instead of one per element.  The products are added in
+// the same order as one element at a time.
+constexpr int kUnroll = 16;
+
+// out[r] = sum_c M[r][c] * v[c] (SQ: M^2), one wave of the team per row.
 template <bool SQ, typename T>
-__device__ __forceinline__ void rowdots(const T* __restrict__ M, int R, int Cn,
+__device__ __forceinline__ void rowdots(const Team& tm, const T* __restrict__ M, int R, int Cn,
                                         const double* __restrict__ v, double* __restrict__ out) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int r = w; r < R; r += kBW) {
+  const int lane = threadIdx.x & 63;
+  for (int r = tm.wave(); r < R; r += tm.nwave()) {
     const T* row = M + static_cast<int64_t>(r) * Cn;
     double acc = 0.0;
-    for (int c = lane; c < Cn; c += 64) {
+    int c = lane;
+    for (; c + (kUnroll - 1) * 64 < Cn; c += kUnroll * 64) {
+      T a[kUnroll];
+      double vv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) a[u] = row[c + 64 * u];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) vv[u] = v[c + 64 * u];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const double d = static_cast<double>(a[u]);
+        acc += (SQ ? d * d : d) * vv[u];
+      }
+    }
+    for (; c < Cn; c += 64) {
       const double a = static_cast<double>(row[c]);
       acc += (SQ ? a * a : a) * v[c];
     }
@@ -141,25 +247,43 @@ __device__ __forceinline__ void rowdots(const T* __restrict__ M, int R, int Cn,
   }
 }
 
-// out[c] = sum_r M[r][c] * w[r] (SQ: M^2): 256-column tiles, four row groups
-// per tile, combined in LDS in group order.
+// out[c] = sum_r M[r][c] * w[r] (SQ: M^2): 64-column tiles spread over the
+// team's workgroups (so even a team of 64 finds work in an 8,000-column
+// operator), sixteen row groups per tile, combined in LDS in group order.
+constexpr int kTileW = 64, kTileRG = kBB / kTileW;
 template <bool SQ, typename T>
-__device__ __forceinline__ void coldots(const T* __restrict__ M, int R, int Cn,
+__device__ __forceinline__ void coldots(const Team& tm, const T* __restrict__ M, int R, int Cn,
                                         const double* __restrict__ w, double* __restrict__ out) {
   __shared__ double red[kBB];
-  const int cc = threadIdx.x & 255, rg = threadIdx.x >> 8;
-  for (int c0 = 0; c0 < Cn; c0 += 256) {
+  const int cc = threadIdx.x & (kTileW - 1), rg = threadIdx.x / kTileW;
+  for (int c0 = tm.r * kTileW; c0 < Cn; c0 += kTileW * tm.G) {
     const int c = c0 + cc;
     double acc = 0.0;
     if (c < Cn) {
-      for (int r = rg; r < R; r += 4) {
+      int r = rg;
+      for (; r + kTileRG * (kUnroll - 1) < R; r += kTileRG * kUnroll) {
+        T a[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) a[u] = M[static_cast<int64_t>(r + kTileRG * u) * Cn + c];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double d = static_cast<double>(a[u]);
+          acc += (SQ ? d * d : d) * w[r + kTileRG * u];
+        }
+      }
+      for (; r < R; r += kTileRG) {
         const double a = static_cast<double>(M[static_cast<int64_t>(r) * Cn + c]);
         acc += (SQ ? a * a : a) * w[r];
       }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
-    if (rg == 0 && c < Cn) out[c] = red[cc] + red[256 + cc] + red[512 + cc] + red[768 + cc];
+    if (rg == 0 && c < Cn) {
+      double t = red[cc];
+#pragma unroll
+      for (int g = 1; g < kTileRG; ++g) t += red[g * kTileW + cc];
+      out[c] = t;
+    }
     __syncthreads();
   }
 }
@@ -178,32 +302,32 @@ struct Inst {
   __device__ double* P(int64_t off) const { return v + off; }
 };
 
-// y = H x into ya (dense: row dots; low rank: h0 x + U (wd * (U^T x))).
+// y = H x into y (dense: row dots; low rank: h0 x + U (wd * (U^T x))).
 template <typename T>
-__device__ __forceinline__ void hess_apply(const Inst<T>& I, const double* x, double* y) {
+__device__ __forceinline__ void hess_apply(Team& tm, const Inst<T>& I, const double* x, double* y) {
   double* g = I.P(I.L.g);
   double* gw = I.P(I.L.gw);
   if (I.hk == 0) {
-    rowdots<false>(I.H, I.n, I.n, x, y);
-    __syncthreads();
+    rowdots<false>(tm, I.H, I.n, I.n, x, y);
+    team_sync(tm);
     return;
   }
-  coldots<false>(I.H, I.n, I.k, x, g);
-  __syncthreads();
-  for (int l = threadIdx.x; l < I.k; l += kBB) gw[l] = I.P(I.L.wd)[l] * g[l];
-  __syncthreads();
-  rowdots<false>(I.H, I.n, I.k, gw, y);
-  __syncthreads();
+  coldots<false>(tm, I.H, I.n, I.k, x, g);
+  team_sync(tm);
+  for (int l = tm.tid(); l < I.k; l += tm.nthr()) gw[l] = I.P(I.L.wd)[l] * g[l];
+  team_sync(tm);
+  rowdots<false>(tm, I.H, I.n, I.k, gw, y);
+  team_sync(tm);
   const double* h0 = I.P(I.L.h0);
-  for (int j = threadIdx.x; j < I.n; j += kBB) y[j] += h0[j] * x[j];
-  __syncthreads();
+  for (int j = tm.tid(); j < I.n; j += tm.nthr()) y[j] += h0[j] * x[j];
+  team_sync(tm);
 }
 
 // Residual stack (eq. 3 with the bound rows) and its norms; returns
 // {stacked, primal, dual, compl}.
 template <typename T>
-__device__ __noinline__ void residuals(const BInst* bi, double* vec, double mu,
-                                    double* nrm) {
+__device__ __noinline__ void residuals(Team& tm, const BInst* bi, double* vec, double mu,
+                                       double* nrm) {
   const Inst<T> I(*bi, vec);
   const int n = I.n, m = I.m;
   const double *x = I.P(I.L.x), *lam = I.P(I.L.lam), *s = I.P(I.L.s);
@@ -211,10 +335,10 @@ __device__ __noinline__ void residuals(const BInst* bi, double* vec, double mu,
   double *res = I.P(I.L.res), *t = I.P(I.L.t), *wv = I.P(I.L.wv), *ya = I.P(I.L.ya), *yh = I.P(I.L.yh);
   const int64_t oH = 0, olA = n, ouA = n + m, olx = n + 2 * m, oux = 2 * n + 2 * m,
                 oc1 = 3 * n + 2 * m, oc2 = 3 * n + 3 * m, oc3 = 3 * n + 4 * m, oc4 = 4 * n + 4 * m;
-  if (m > 0) rowdots<false>(I.A, m, n, x, t);
-  __syncthreads();
-  double pr = 0.0, du = 0.0, co = 0.0;
-  for (int i = threadIdx.x; i < m; i += kBB) {
+  if (m > 0) rowdots<false>(tm, I.A, m, n, x, t);
+  team_sync(tm);
+  double v[3] = {0.0, 0.0, 0.0};   // primal, dual, compl
+  for (int i = tm.tid(); i < m; i += tm.nthr()) {
     const bool hl = blo(lA[i]), hu = bhi(uA[i]);
     const double ll = lam[i], lu = lam[m + i], sl = s[i], su = s[m + i];
     const double rl = hl ? t[i] - sl - lA[i] : 0.0;
@@ -223,15 +347,15 @@ __device__ __noinline__ void residuals(const BInst* bi, double* vec, double mu,
     const double c2 = hu ? lu * su - mu : 0.0;
     res[olA + i] = rl; res[ouA + i] = ru; res[oc1 + i] = c1; res[oc2 + i] = c2;
     wv[i] = (hu ? lu : 0.0) - (hl ? ll : 0.0);
-    pr += rl * rl + ru * ru;
-    co += c1 * c1 + c2 * c2;
+    v[0] += rl * rl + ru * ru;
+    v[2] += c1 * c1 + c2 * c2;
   }
-  __syncthreads();
-  if (m > 0) coldots<false>(I.A, m, n, wv, ya);
-  __syncthreads();
-  hess_apply(I, x, yh);
+  team_sync(tm);
+  if (m > 0) coldots<false>(tm, I.A, m, n, wv, ya);
+  team_sync(tm);
+  hess_apply(tm, I, x, yh);
   const double* c = I.P(I.L.c);
-  for (int j = threadIdx.x; j < n; j += kBB) {
+  for (int j = tm.tid(); j < n; j += tm.nthr()) {
     const bool hl = blo(lx[j]), hu = bhi(ux[j]);
     const double llx = hl ? lam[2 * m + j] : 0.0, lux = hu ? lam[2 * m + n + j] : 0.0;
     const double slx = s[2 * m + j], sux = s[2 * m + n + j];
@@ -241,22 +365,20 @@ __device__ __noinline__ void residuals(const BInst* bi, double* vec, double mu,
     const double c3 = hl ? llx * slx - mu : 0.0;
     const double c4 = hu ? lux * sux - mu : 0.0;
     res[oH + j] = rH; res[olx + j] = rlx; res[oux + j] = rux; res[oc3 + j] = c3; res[oc4 + j] = c4;
-    du += rH * rH;
-    pr += rlx * rlx + rux * rux;
-    co += c3 * c3 + c4 * c4;
+    v[1] += rH * rH;
+    v[0] += rlx * rlx + rux * rux;
+    v[2] += c3 * c3 + c4 * c4;
   }
-  pr = wg_sum(pr);
-  du = wg_sum(du);
-  co = wg_sum(co);
-  nrm[0] = sqrt(pr + du + co);
-  nrm[1] = sqrt(pr);
-  nrm[2] = sqrt(du);
-  nrm[3] = sqrt(co);
+  team_reduce<3>(tm, v);
+  nrm[0] = sqrt(v[0] + v[1] + v[2]);
+  nrm[1] = sqrt(v[0]);
+  nrm[2] = sqrt(v[1]);
+  nrm[3] = sqrt(v[2]);
 }
 
 // D, the eq. 9 right-hand side, diag(K) and Q's diagonal (eqs. 8, 9).
 template <typename T>
-__device__ __noinline__ void newton_system(const BInst* bi, double* vec, double mu) {
+__device__ __noinline__ void newton_system(Team& tm, const BInst* bi, double* vec, double mu) {
   const Inst<T> I(*bi, vec);
   const int n = I.n, m = I.m;
   const double *lam = I.P(I.L.lam), *s = I.P(I.L.s), *res = I.P(I.L.res);
@@ -265,7 +387,7 @@ __device__ __noinline__ void newton_system(const BInst* bi, double* vec, double 
   double *wv = I.P(I.L.wv), *jw = I.P(I.L.jw), *ya = I.P(I.L.ya), *yh = I.P(I.L.yh);
   const int64_t olA = n, ouA = n + m, olx = n + 2 * m, oux = 2 * n + 2 * m,
                 oc1 = 3 * n + 2 * m, oc2 = 3 * n + 3 * m, oc3 = 3 * n + 4 * m, oc4 = 4 * n + 4 * m;
-  for (int i = threadIdx.x; i < m; i += kBB) {
+  for (int i = tm.tid(); i < m; i += tm.nthr()) {
     const bool hl = blo(lA[i]), hu = bhi(uA[i]);
     const double ll = lam[i], lu = lam[m + i];
     const double dL = hl ? s[i] / ll : 1.0, dU = hu ? s[m + i] / lu : 1.0;
@@ -277,14 +399,14 @@ __device__ __noinline__ void newton_system(const BInst* bi, double* vec, double 
     wv[i] = (hl ? 2.0 * r2L / dL : 0.0) - (hu ? 2.0 * r2U / dU : 0.0);
     jw[i] = (hl ? 2.0 / dL : 0.0) + (hu ? 2.0 / dU : 0.0);
   }
-  __syncthreads();
+  team_sync(tm);
   if (m > 0) {
-    coldots<false>(I.A, m, n, wv, ya);
-    coldots<true>(I.A, m, n, jw, yh);
+    coldots<false>(tm, I.A, m, n, wv, ya);
+    coldots<true>(tm, I.A, m, n, jw, yh);
   }
-  __syncthreads();
+  team_sync(tm);
   const double *diagH = I.P(I.L.diagH), *h0 = I.P(I.L.h0);
-  for (int j = threadIdx.x; j < n; j += kBB) {
+  for (int j = tm.tid(); j < n; j += tm.nthr()) {
     const bool hl = blo(lx[j]), hu = bhi(ux[j]);
     const double llx = hl ? lam[2 * m + j] : 0.0, lux = hu ? lam[2 * m + n + j] : 0.0;
     const double slx = hl ? s[2 * m + j] : 1.0, sux = hu ? s[2 * m + n + j] : 1.0;
@@ -296,19 +418,21 @@ __device__ __noinline__ void newton_system(const BInst* bi, double* vec, double 
     jd[j] = diagH[j] + qb + (m > 0 ? yh[j] : 0.0);
     qd[j] = (I.hk == 1 ? h0[j] : 0.0) + qb;
   }
-  __syncthreads();
+  team_sync(tm);
 }
 
-// q = K p (eq. 9, matrix-free); returns p . q.
+// q = K p (eq. 9, matrix-free); returns p . q.  The row products A p and, for
+// a dense H, H p share the first phase (both only read p).
 template <typename T>
-__device__ __forceinline__ double kkt_apply(const Inst<T>& I, const double* p, double* q) {
+__device__ __forceinline__ double kkt_apply(Team& tm, const Inst<T>& I, const double* p, double* q) {
   const int n = I.n, m = I.m;
   const double *lA = I.P(I.L.lA), *uA = I.P(I.L.uA), *dl = I.P(I.L.dl), *qd = I.P(I.L.qd);
   double *t = I.P(I.L.t), *wv = I.P(I.L.wv), *ya = I.P(I.L.ya), *yh = I.P(I.L.yh);
-  if (m > 0) rowdots<false>(I.A, m, n, p, t);
-  __syncthreads();
+  if (m > 0) rowdots<false>(tm, I.A, m, n, p, t);
+  if (I.hk == 0) rowdots<false>(tm, I.H, n, n, p, yh);
+  team_sync(tm);
   double dot = 0.0;
-  for (int i = threadIdx.x; i < m; i += kBB) {
+  for (int i = tm.tid(); i < m; i += tm.nthr()) {
     const bool hl = blo(lA[i]), hu = bhi(uA[i]);
     const double pl = p[n + i], pu = p[n + m + i], dL = dl[i], dU = dl[m + i];
     const double ylo = (hl ? t[i] : 0.0) + dL * pl;
@@ -318,135 +442,128 @@ __device__ __forceinline__ double kkt_apply(const Inst<T>& I, const double* p, d
     wv[i] = (hl ? 2.0 * t[i] / dL + pl : 0.0) - (hu ? -2.0 * t[i] / dU + pu : 0.0);
     dot += pl * ylo + pu * yup;
   }
-  __syncthreads();
-  if (m > 0) coldots<false>(I.A, m, n, wv, ya);
-  __syncthreads();
-  if (I.hk == 0) {
-    rowdots<false>(I.H, n, n, p, yh);
-    __syncthreads();
-  } else {
+  team_sync(tm);
+  if (m > 0) coldots<false>(tm, I.A, m, n, wv, ya);
+  if (I.hk != 0) {
     double *g = I.P(I.L.g), *gw = I.P(I.L.gw);
-    coldots<false>(I.H, n, I.k, p, g);
-    __syncthreads();
-    for (int l = threadIdx.x; l < I.k; l += kBB) gw[l] = I.P(I.L.wd)[l] * g[l];
-    __syncthreads();
-    rowdots<false>(I.H, n, I.k, gw, yh);
-    __syncthreads();
+    team_sync(tm);
+    coldots<false>(tm, I.H, n, I.k, p, g);
+    team_sync(tm);
+    for (int l = tm.tid(); l < I.k; l += tm.nthr()) gw[l] = I.P(I.L.wd)[l] * g[l];
+    team_sync(tm);
+    rowdots<false>(tm, I.H, n, I.k, gw, yh);
   }
-  for (int j = threadIdx.x; j < n; j += kBB) {
+  team_sync(tm);
+  for (int j = tm.tid(); j < n; j += tm.nthr()) {
     const double y = (m > 0 ? ya[j] : 0.0) + yh[j] + qd[j] * p[j];
     q[j] = y;
     dot += p[j] * y;
   }
-  return wg_sum(dot);
+  return team_sum(tm, dot);
 }
 
 // Jacobi PCG on eq. 9 into sol; returns iterations (negative: status code).
 template <typename T>
-__device__ __noinline__ int pcg(const BInst* bi, double* vec, double tol, int maxit,
+__device__ __noinline__ int pcg(Team& tm, const BInst* bi, double* vec, double tol, int maxit,
                                int* converged_out) {
   const Inst<T> I(*bi, vec);
   const int N = I.n + 2 * I.m;
   double *x = I.P(I.L.sol), *r = I.P(I.L.r), *z = I.P(I.L.z), *p = I.P(I.L.p), *q = I.P(I.L.q);
   const double *rhs = I.P(I.L.rhs), *jd = I.P(I.L.jd);
-  double rz = 0.0, rr = 0.0;
-  for (int i = threadIdx.x; i < N; i += kBB) {
+  double v[2] = {0.0, 0.0};   // r.z, r.r
+  for (int i = tm.tid(); i < N; i += tm.nthr()) {
     const double ri = rhs[i], zi = ri / jd[i];
     x[i] = 0.0; r[i] = ri; z[i] = zi; p[i] = zi;
-    rz += ri * zi;
-    rr += ri * ri;
+    v[0] += ri * zi;
+    v[1] += ri * ri;
   }
-  rz = wg_sum(rz);
-  const double nb = sqrt(wg_sum(rr));
+  team_reduce<2>(tm, v);
+  double rz = v[0];
+  const double nb = sqrt(v[1]);
   *converged_out = 0;
   if (!(nb > 0.0)) {
     *converged_out = nb == 0.0;
     return nb == 0.0 ? 0 : QP_ERR_NUMERIC_CODE;
   }
   for (int k = 0; k < maxit; ++k) {
-    const double pq = kkt_apply(I, p, q);
+    const double pq = kkt_apply(tm, I, p, q);
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz))
       return (isfinite(pq) && isfinite(rz)) ? QP_ERR_NOT_SPD_CODE : QP_ERR_NUMERIC_CODE;
     const double alpha = rz / pq;
-    double rzn = 0.0, rn = 0.0;
-    for (int i = threadIdx.x; i < N; i += kBB) {
+    double w[2] = {0.0, 0.0};   // r.z, r.r of the new residual
+    for (int i = tm.tid(); i < N; i += tm.nthr()) {
       x[i] += alpha * p[i];
       const double ri = r[i] - alpha * q[i], zi = ri / jd[i];
       r[i] = ri; z[i] = zi;
-      rzn += ri * zi;
-      rn += ri * ri;
+      w[0] += ri * zi;
+      w[1] += ri * ri;
     }
-    rzn = wg_sum(rzn);
-    rn = wg_sum(rn);
-    if (sqrt(rn) <= tol * nb) {
+    team_reduce<2>(tm, w);
+    if (sqrt(w[1]) <= tol * nb) {
       *converged_out = 1;
       return k + 1;
     }
-    const double beta = rzn / rz;
-    rz = rzn;
-    for (int i = threadIdx.x; i < N; i += kBB) p[i] = z[i] + beta * p[i];
-    __syncthreads();
+    const double beta = w[0] / rz;
+    rz = w[0];
+    for (int i = tm.tid(); i < N; i += tm.nthr()) p[i] = z[i] + beta * p[i];
+    team_sync(tm);
   }
   return maxit;
 }
 
 // Recovery (eq. 7) and the ratio test (eq. 10): returns alpha_x, alpha_lam.
 template <typename T>
-__device__ __noinline__ void recover_ratio(const BInst* bi, double* vec, double gamma,
-                                        double* alphas) {
+__device__ __noinline__ void recover_ratio(Team& tm, const BInst* bi, double* vec, double gamma,
+                                           double* alphas) {
   const Inst<T> I(*bi, vec);
-  double ax, al;
   const int n = I.n, m = I.m;
   const double *lam = I.P(I.L.lam), *s = I.P(I.L.s), *res = I.P(I.L.res);
   const double *lA = I.P(I.L.lA), *uA = I.P(I.L.uA), *lx = I.P(I.L.lx), *ux = I.P(I.L.ux);
   double *dx = I.P(I.L.sol), *dlam = I.P(I.L.sol) + n, *ds = I.P(I.L.ds), *t = I.P(I.L.t);
   const int64_t olA = n, ouA = n + m, olx = n + 2 * m, oux = 2 * n + 2 * m, oc3 = 3 * n + 4 * m,
                 oc4 = 4 * n + 4 * m;
-  if (m > 0) rowdots<false>(I.A, m, n, dx, t);
-  __syncthreads();
-  double ms = INFINITY, ml = INFINITY;
-  for (int i = threadIdx.x; i < m; i += kBB) {
+  if (m > 0) rowdots<false>(tm, I.A, m, n, dx, t);
+  team_sync(tm);
+  double mn[2] = {INFINITY, INFINITY};   // slacks, multipliers
+  for (int i = tm.tid(); i < m; i += tm.nthr()) {
     const bool hl = blo(lA[i]), hu = bhi(uA[i]);
     const double dsl = hl ? t[i] + res[olA + i] : 0.0;
     const double dsu = hu ? -t[i] + res[ouA + i] : 0.0;
     ds[i] = dsl; ds[m + i] = dsu;
     const double dll = hl ? dlam[i] : 0.0, dlu = hu ? dlam[m + i] : 0.0;
     dlam[i] = dll; dlam[m + i] = dlu;
-    if (hl && dsl < 0.0) ms = fmin(ms, -s[i] / dsl);
-    if (hu && dsu < 0.0) ms = fmin(ms, -s[m + i] / dsu);
-    if (hl && dll < 0.0) ml = fmin(ml, -lam[i] / dll);
-    if (hu && dlu < 0.0) ml = fmin(ml, -lam[m + i] / dlu);
+    if (hl && dsl < 0.0) mn[0] = fmin(mn[0], -s[i] / dsl);
+    if (hu && dsu < 0.0) mn[0] = fmin(mn[0], -s[m + i] / dsu);
+    if (hl && dll < 0.0) mn[1] = fmin(mn[1], -lam[i] / dll);
+    if (hu && dlu < 0.0) mn[1] = fmin(mn[1], -lam[m + i] / dlu);
   }
-  for (int j = threadIdx.x; j < n; j += kBB) {
+  for (int j = tm.tid(); j < n; j += tm.nthr()) {
     const bool hl = blo(lx[j]), hu = bhi(ux[j]);
     double dsl = 0.0, dsu = 0.0, dll = 0.0, dlu = 0.0;
     if (hl) {
       const double slx = s[2 * m + j], llx = lam[2 * m + j];
       dsl = dx[j] + res[olx + j];
       dll = -(res[oc3 + j] + llx * dsl) / slx;
-      if (dsl < 0.0) ms = fmin(ms, -slx / dsl);
-      if (dll < 0.0) ml = fmin(ml, -llx / dll);
+      if (dsl < 0.0) mn[0] = fmin(mn[0], -slx / dsl);
+      if (dll < 0.0) mn[1] = fmin(mn[1], -llx / dll);
     }
     if (hu) {
       const double sux = s[2 * m + n + j], lux = lam[2 * m + n + j];
       dsu = -dx[j] + res[oux + j];
       dlu = -(res[oc4 + j] + lux * dsu) / sux;
-      if (dsu < 0.0) ms = fmin(ms, -sux / dsu);
-      if (dlu < 0.0) ml = fmin(ml, -lux / dlu);
+      if (dsu < 0.0) mn[0] = fmin(mn[0], -sux / dsu);
+      if (dlu < 0.0) mn[1] = fmin(mn[1], -lux / dlu);
     }
     ds[2 * m + j] = dsl; ds[2 * m + n + j] = dsu;
     dlam[2 * m + j] = dll; dlam[2 * m + n + j] = dlu;
   }
-  ms = wg_min(ms);
-  ml = wg_min(ml);
-  ax = fmin(1.0, gamma * ms);
-  al = fmin(1.0, gamma * ml);
-  alphas[0] = ax;
-  alphas[1] = al;
+  team_reduce<2, true>(tm, mn);
+  alphas[0] = fmin(1.0, gamma * mn[0]);
+  alphas[1] = fmin(1.0, gamma * mn[1]);
 }
 
 template <typename T>
-__device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
+__device__ __forceinline__ void solve_one(Team& tm, const BArgs<T>& a, int id) {
   const Inst<T> I(a.inst[id], a.vec);
   const int n = I.n, m = I.m;
   const BOpts& o = a.o;
@@ -455,14 +572,15 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
   // diag(H)
   double* diagH = I.P(I.L.diagH);
   if (I.hk == 0) {
-    for (int j = threadIdx.x; j < n; j += kBB) diagH[j] = static_cast<double>(I.H[static_cast<int64_t>(j) * n + j]);
+    for (int j = tm.tid(); j < n; j += tm.nthr())
+      diagH[j] = static_cast<double>(I.H[static_cast<int64_t>(j) * n + j]);
   } else {
-    rowdots<true>(I.H, n, I.k, I.P(I.L.wd), diagH);
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += kBB) diagH[j] += I.P(I.L.h0)[j];
+    rowdots<true>(tm, I.H, n, I.k, I.P(I.L.wd), diagH);
+    team_sync(tm);
+    for (int j = tm.tid(); j < n; j += tm.nthr()) diagH[j] += I.P(I.L.h0)[j];
   }
   // starting point
-  for (int j = threadIdx.x; j < n; j += kBB) {
+  for (int j = tm.tid(); j < n; j += tm.nthr()) {
     const bool hl = blo(lx[j]), hu = bhi(ux[j]);
     double xj = 0.0;
     if (hl && hu) xj = 0.5 * (lx[j] + ux[j]);
@@ -474,26 +592,26 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
     lam[2 * m + j] = hl ? 1.0 : 0.0;
     lam[2 * m + n + j] = hu ? 1.0 : 0.0;
   }
-  __syncthreads();
-  if (m > 0) rowdots<false>(I.A, m, n, x, t);
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += kBB) {
+  team_sync(tm);
+  if (m > 0) rowdots<false>(tm, I.A, m, n, x, t);
+  team_sync(tm);
+  for (int i = tm.tid(); i < m; i += tm.nthr()) {
     const bool hl = blo(lA[i]), hu = bhi(uA[i]);
     s[i] = hl ? fmax(t[i] - lA[i], 1.0) : 0.0;
     s[m + i] = hu ? fmax(uA[i] - t[i], 1.0) : 0.0;
     lam[i] = hl ? 1.0 : 0.0;
     lam[m + i] = hu ? 1.0 : 0.0;
   }
-  __syncthreads();
+  team_sync(tm);
   double mu = o.mu0, nrm[4] = {0, 0, 0, 0};
   int it = 0, status = QP_IPM_MAX_ITER, hits = 0;
   int64_t total = 0;
   const BInst* bi = a.inst + id;
   for (it = 1; it <= o.max_iter; ++it) {
-    residuals<T>(bi, a.vec, mu, nrm);
-    newton_system<T>(bi, a.vec, mu);
+    residuals<T>(tm, bi, a.vec, mu, nrm);
+    newton_system<T>(tm, bi, a.vec, mu);
     int conv = 0;
-    const int pit = pcg<T>(bi, a.vec, o.cg_tol, o.cg_maxit, &conv);
+    const int pit = pcg<T>(tm, bi, a.vec, o.cg_tol, o.cg_maxit, &conv);
     if (pit < 0) {
       status = pit;
       break;
@@ -501,16 +619,16 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
     total += pit;
     if (!conv) ++hits;
     double al2[2];
-    recover_ratio<T>(bi, a.vec, o.gamma, al2);
+    recover_ratio<T>(tm, bi, a.vec, o.gamma, al2);
     const double ax = al2[0], al = al2[1];
     const double *dx = I.P(I.L.sol), *dlam = I.P(I.L.sol) + n, *ds = I.P(I.L.ds);
-    for (int j = threadIdx.x; j < n; j += kBB) x[j] += ax * dx[j];
-    for (int q = threadIdx.x; q < 2 * m + 2 * n; q += kBB) {
+    for (int j = tm.tid(); j < n; j += tm.nthr()) x[j] += ax * dx[j];
+    for (int q = tm.tid(); q < 2 * m + 2 * n; q += tm.nthr()) {
       s[q] += ax * ds[q];      // absent sides carry zero steps
       lam[q] += al * dlam[q];
     }
-    __syncthreads();
-    residuals<T>(bi, a.vec, mu, nrm);
+    team_sync(tm);
+    residuals<T>(tm, bi, a.vec, mu, nrm);
     if (!isfinite(nrm[0])) {
       status = QP_ERR_NUMERIC_CODE;
       break;
@@ -525,33 +643,60 @@ __device__ __forceinline__ void solve_one(const BArgs<T>& a, int id) {
   }
   // objective 1/2 x^T H x + c^T x
   double* yh = I.P(I.L.yh);
-  hess_apply(I, x, yh);
+  hess_apply(tm, I, x, yh);
   double ob = 0.0;
   const double* c = I.P(I.L.c);
-  for (int j = threadIdx.x; j < n; j += kBB) ob += x[j] * (0.5 * yh[j] + c[j]);
-  ob = wg_sum(ob);
-  if (threadIdx.x == 0) {
+  for (int j = tm.tid(); j < n; j += tm.nthr()) ob += x[j] * (0.5 * yh[j] + c[j]);
+  ob = team_sum(tm, ob);
+  if (tm.r == 0 && threadIdx.x == 0) {
     BResult r{};
     r.mu_final = mu; r.rnorm = nrm[0]; r.primal = nrm[1]; r.dual = nrm[2]; r.compl_ = nrm[3];
     r.objective = ob; r.status = status; r.iterations = it > o.max_iter ? o.max_iter : it;
     r.cg_hits = hits; r.total_cg = total;
     a.out[id] = r;
   }
-  __syncthreads();
+  team_sync(tm);
 }
 
+// Every workgroup belongs to a team (of one without a plan); a team draws
+// instances from its queue until the queue is empty.  The team's first
+// member draws and passes the index to the others through the team's state.
 template <typename T>
 __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
   __shared__ int slot;
+  Team tm;
+  const int32_t* order = a.order;
+  int32_t count = a.count;
+  int32_t* next = a.next;
+  tm.G = 1; tm.r = 0; tm.ts = nullptr; tm.abort = nullptr; tm.spin_max = 0;
+  if (a.plan.team_of) {
+    const int t = a.plan.team_of[blockIdx.x];
+    tm.G = a.plan.size[t];
+    tm.r = static_cast<int>(blockIdx.x) - a.plan.first[t];
+    tm.ts = a.plan.sync + t;
+    tm.abort = a.plan.abort;
+    tm.spin_max = a.plan.spin_max;
+    const int q = a.plan.queue[t];
+    order = a.plan.qorder + a.plan.qstart[q];
+    count = a.plan.qcount[q];
+    next = a.plan.qnext + q;
+  }
+  tm.gen = 0;
+  tm.slot = 0;
   for (;;) {
-    if (threadIdx.x == 0) slot = atomicAdd(a.next, 1);
+    if (tm.r == 0 && threadIdx.x == 0) {
+      slot = atomicAdd(next, 1);
+      if (tm.G > 1) tm.ts->cur = slot;
+    }
+    team_sync(tm);
+    if (tm.r != 0 && threadIdx.x == 0) slot = tm.ts->cur;
     __syncthreads();
     // the slot is the same for the whole workgroup: make that visible to the
     // compiler so the instance's sizes and offsets live in scalar registers
     const int q = __builtin_amdgcn_readfirstlane(slot);
     __syncthreads();
-    if (q >= a.count) break;
-    solve_one(a, __builtin_amdgcn_readfirstlane(a.order[q]));
+    if (q >= count) break;
+    solve_one(tm, a, __builtin_amdgcn_readfirstlane(order[q]));
   }
 }
 
@@ -641,8 +786,16 @@ struct qp_batch_s {
   double* d_vec = nullptr;
   BResult* d_out = nullptr;
   std::vector<BResult> out;
+  // team launches: the team size of each instance (all 1: one workgroup each)
+  std::vector<int32_t> team;
+  int32_t* d_plan = nullptr;      // team_of | first | size | queue | qstart | qcount | qnext | qorder | abort
+  int64_t plan_cap = 0;           // int32 entries of d_plan
+  TeamSync* d_sync = nullptr;
+  int sync_cap = 0;
+  int last_grid = 0, last_teams = 0;
   ~qp_batch_s() {
-    for (void* p : {(void*)d_inst, (void*)d_order, (void*)d_next, d_vals, (void*)d_vec, (void*)d_out})
+    for (void* p : {(void*)d_inst, (void*)d_order, (void*)d_next, d_vals, (void*)d_vec, (void*)d_out,
+                    (void*)d_plan, (void*)d_sync})
       if (p) (void)hipFree(p);
   }
 };
@@ -767,6 +920,128 @@ static qp_status batch_create_impl(qp_batch b, const qp_desc* ds, int32_t count)
   BCHK(hipMemcpyAsync(b->d_vec, hv.data(), sizeof(double) * vecs, hipMemcpyHostToDevice, b->st));
   BCHK(hipStreamSynchronize(b->st));
   b->out.resize(count);
+  b->team.assign(count, 1);
+  return QP_OK;
+}
+
+// Work of one PCG iteration of an instance (operator entries read).
+static double inst_work(const BInst& I) {
+  return 2.0 * I.m * (double)I.n + (double)I.n * (I.hkind ? 2.0 * I.k : (double)I.n);
+}
+
+// Workgroups of the batch kernel that fit on the device at once.
+static qp_status coresident(qp_batch b, int* out) {
+  int dev = 0, cus = 0, per = 0;
+  BCHK(hipGetDevice(&dev));
+  BCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (b->f32) BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_ipm<float>, kBB, 0));
+  else BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_ipm<double>, kBB, 0));
+  *out = std::max(1, cus * per);
+  return QP_OK;
+}
+
+// Plans a team launch on at most `cap` workgroups: the instances of each team
+// size form a queue (largest work first); each size gets workgroups in
+// proportion to its instances' work, as whole teams (at least one).
+static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
+  std::vector<int> sizes;
+  for (int g : b->team) if (std::find(sizes.begin(), sizes.end(), g) == sizes.end()) sizes.push_back(g);
+  std::sort(sizes.begin(), sizes.end(), std::greater<int>());
+  const int nq = (int)sizes.size();
+  std::vector<double> qwork(nq, 0.0);
+  std::vector<std::vector<int32_t>> qinst(nq);
+  std::vector<int32_t> order(b->count);
+  for (int i = 0; i < b->count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return inst_work(b->inst[x]) > inst_work(b->inst[y]); });
+  for (int i : order) {
+    const int q = (int)(std::find(sizes.begin(), sizes.end(), b->team[i]) - sizes.begin());
+    qinst[q].push_back(i);
+    qwork[q] += inst_work(b->inst[i]);
+  }
+  double tot = 0.0;
+  for (double w : qwork) tot += w;
+  // teams per queue: at least one, at most one per instance, within cap
+  std::vector<int> nteams(nq, 1);
+  int used = 0;
+  for (int q = 0; q < nq; ++q) used += sizes[q];
+  if (used > cap) {
+    b->err = "team sizes need " + std::to_string(used) + " workgroups at once; " + std::to_string(cap) +
+             " fit on the device";
+    return QP_ERR_ARG;
+  }
+  for (int q = 0; q < nq; ++q) {
+    const int want = (int)((double)cap * qwork[q] / std::max(tot, 1e-300) / sizes[q]);
+    nteams[q] = std::max(1, std::min<int>((int)qinst[q].size(), want));
+  }
+  auto total_wg = [&]() {
+    int t = 0;
+    for (int q = 0; q < nq; ++q) t += nteams[q] * sizes[q];
+    return t;
+  };
+  while (total_wg() > cap) {   // trim the queue with the most workgroups per unit of work
+    int worst = -1;
+    double ratio = -1.0;
+    for (int q = 0; q < nq; ++q)
+      if (nteams[q] > 1) {
+        const double r = nteams[q] * sizes[q] / std::max(qwork[q], 1e-300);
+        if (r > ratio) { ratio = r; worst = q; }
+      }
+    if (worst < 0) break;
+    --nteams[worst];
+  }
+  int teams = 0;
+  for (int q = 0; q < nq; ++q) teams += nteams[q];
+  const int W = total_wg();
+  // host arrays, one upload
+  std::vector<int32_t> team_of(W), first(teams), size(teams), queue(teams), qstart(nq), qcount(nq),
+      qnext(nq, 0), qorder;
+  int t = 0, w = 0;
+  for (int q = 0; q < nq; ++q) {
+    qstart[q] = (int32_t)qorder.size();
+    qcount[q] = (int32_t)qinst[q].size();
+    qorder.insert(qorder.end(), qinst[q].begin(), qinst[q].end());
+    for (int k = 0; k < nteams[q]; ++k, ++t) {
+      first[t] = w;
+      size[t] = sizes[q];
+      queue[t] = q;
+      for (int r = 0; r < sizes[q]; ++r) team_of[w++] = t;
+    }
+  }
+  std::vector<int32_t> blob;
+  auto put = [&](const std::vector<int32_t>& v) {
+    const int64_t off = (int64_t)blob.size();
+    blob.insert(blob.end(), v.begin(), v.end());
+    return off;
+  };
+  const int64_t o_team = put(team_of), o_first = put(first), o_size = put(size), o_queue = put(queue),
+                o_qstart = put(qstart), o_qcount = put(qcount), o_qnext = put(qnext),
+                o_qorder = put(qorder), o_abort = put({0});
+  if ((int64_t)blob.size() > b->plan_cap) {
+    if (b->d_plan) (void)hipFree(b->d_plan);
+    b->d_plan = nullptr;
+    b->plan_cap = 0;
+    BCHK(hipMalloc((void**)&b->d_plan, sizeof(int32_t) * blob.size()));
+    b->plan_cap = (int64_t)blob.size();
+  }
+  if (teams > b->sync_cap) {
+    if (b->d_sync) (void)hipFree(b->d_sync);
+    b->d_sync = nullptr;
+    b->sync_cap = 0;
+    BCHK(hipMalloc((void**)&b->d_sync, sizeof(TeamSync) * teams));
+    b->sync_cap = teams;
+  }
+  BCHK(hipMemcpyAsync(b->d_plan, blob.data(), sizeof(int32_t) * blob.size(), hipMemcpyHostToDevice, b->st));
+  BCHK(hipMemsetAsync(b->d_sync, 0, sizeof(TeamSync) * teams, b->st));
+  int32_t* P = b->d_plan;
+  plan->team_of = P + o_team; plan->first = P + o_first; plan->size = P + o_size;
+  plan->queue = P + o_queue; plan->qstart = P + o_qstart; plan->qcount = P + o_qcount;
+  plan->qnext = P + o_qnext; plan->qorder = P + o_qorder; plan->sync = b->d_sync;
+  plan->abort = P + o_abort;
+  plan->spin_max = 1 << 26;
+  *grid = W;
+  b->last_grid = W;
+  b->last_teams = teams;
   return QP_OK;
 }
 
@@ -814,21 +1089,40 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
     b->err = "invalid ipm_options";
     return QP_ERR_ARG;
   }
+  const bool teams = std::any_of(b->team.begin(), b->team.end(), [](int g) { return g > 1; });
+  TeamPlan plan{};
   int grid = workgroups > 0 ? workgroups : 512;
-  grid = std::min(grid, b->count);
+  if (teams) {
+    // every member of a team must be resident while it waits for the others:
+    // a cooperative launch within the device's co-resident workgroups
+    int cap = 0;
+    qp_status cs = coresident(b, &cap);
+    if (cs != QP_OK) return cs;
+    if (workgroups > 0) cap = std::min(cap, workgroups);
+    cs = build_plan(b, cap, &plan, &grid);
+    if (cs != QP_OK) return cs;
+  } else {
+    grid = std::min(grid, b->count);
+    b->last_grid = grid;
+    b->last_teams = grid;
+  }
   BCHK(hipMemsetAsync(b->d_next, 0, sizeof(int32_t), b->st));
   hipEvent_t e0, e1;
   BCHK(hipEventCreate(&e0));
   BCHK(hipEventCreate(&e1));
   BCHK(hipEventRecord(e0, b->st));
-  if (b->f32) {
-    BArgs<float> a{b->d_inst, b->d_order, b->count, b->d_next, b->d_vec, b->d_out, bo};
-    k_batch_ipm<float><<<grid, kBB, 0, b->st>>>(a);
-  } else {
-    BArgs<double> a{b->d_inst, b->d_order, b->count, b->d_next, b->d_vec, b->d_out, bo};
-    k_batch_ipm<double><<<grid, kBB, 0, b->st>>>(a);
-  }
-  BCHK(hipGetLastError());
+  auto go = [&](auto* tag) -> hipError_t {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    BArgs<T> a{b->d_inst, b->d_order, b->count, b->d_next, b->d_vec, b->d_out, bo, plan};
+    if (!teams) {
+      k_batch_ipm<T><<<grid, kBB, 0, b->st>>>(a);
+      return hipGetLastError();
+    }
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_ipm<T>), dim3(grid),
+                                      dim3(kBB), args, 0, b->st);
+  };
+  BCHK(b->f32 ? go((float*)nullptr) : go((double*)nullptr));
   BCHK(hipEventRecord(e1, b->st));
   BCHK(hipMemcpyAsync(b->out.data(), b->d_out, sizeof(BResult) * b->count, hipMemcpyDeviceToHost, b->st));
   BCHK(hipStreamSynchronize(b->st));
@@ -856,8 +1150,40 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
     if (r.status == QP_ERR_NOT_SPD_CODE) worst = QP_ERR_NOT_SPD;
     else if (r.status == QP_ERR_NUMERIC_CODE && worst == QP_OK) worst = QP_ERR_NUMERIC;
   }
+  if (teams) {
+    int32_t ab = 0;
+    BCHK(hipMemcpy(&ab, plan.abort, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (ab) {
+      b->err = "a team barrier wait gave up (members not resident together): results invalid";
+      return QP_ERR_HIP;
+    }
+  }
   if (worst != QP_OK) b->err = "at least one instance stopped on a numerical error (see its info)";
   return worst;
+}
+
+qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size) {
+  if (!b) return QP_ERR_ARG;
+  std::vector<int32_t> t(b->count, 1);
+  if (team_size) {
+    for (int i = 0; i < b->count; ++i) {
+      const int g = team_size[i];
+      if (g < 1 || g > kTeamMax || (g & (g - 1))) {
+        b->err = "team sizes are powers of two from 1 to " + std::to_string(kTeamMax);
+        return QP_ERR_ARG;
+      }
+      t[i] = g;
+    }
+  }
+  b->team = t;
+  return QP_OK;
+}
+
+qp_status qp_batch_launch_shape(qp_batch b, int32_t* workgroups, int32_t* teams) {
+  if (!b) return QP_ERR_ARG;
+  if (workgroups) *workgroups = b->last_grid;
+  if (teams) *teams = b->last_teams;
+  return QP_OK;
 }
 
 // Per-device address of `scratch`, looked up once per device with that

@@ -88,7 +88,7 @@ EXPORTS = [
     "qp_profile_begin", "qp_profile_end", "qp_operator_bytes", "qp_operator_layout",
     "qp_update_data", "qp_fused_layout",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
-    "qp_batch_last_error", "ipm_solve_dense_noalloc",
+    "qp_batch_last_error", "ipm_solve_dense_noalloc", "qp_batch_set_teams", "qp_batch_launch_shape",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate", "fused")
 
@@ -131,6 +131,8 @@ def _load():
         "ipm_solve_batch": (C.c_int, [vp, C.POINTER(IpmOptions), C.c_int32, C.POINTER(IpmInfo)]),
         "qp_batch_get_solution": (C.c_int, [vp, C.c_int32, vp, vp, vp]),
         "qp_batch_last_error": (C.c_char_p, [vp]),
+        "qp_batch_set_teams": (C.c_int, [vp, _i32p]),
+        "qp_batch_launch_shape": (C.c_int, [vp, _i32p, _i32p]),
         "ipm_solve_dense_noalloc": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
                                               C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo), vp]),
     }
@@ -457,6 +459,25 @@ class QPBatch:
         if h is not None and h.value:
             LIB.qp_batch_destroy(h)
             self.h = None
+
+    def set_teams(self, sizes=None):
+        """Workgroups per instance (powers of two, 1..64; None: all 1)."""
+        arr = None
+        if sizes is not None:
+            arr = (C.c_int32 * len(self.specs))(*[int(g) for g in sizes])
+        st = LIB.qp_batch_set_teams(self.h, arr)
+        if st != QP_OK:
+            raise QPError(st, LIB.qp_batch_last_error(self.h).decode())
+
+    def launch_shape(self):
+        """(workgroups, teams) of the last solve's launch."""
+        w, t = C.c_int32(), C.c_int32()
+        self._check_status(LIB.qp_batch_launch_shape(self.h, C.byref(w), C.byref(t)))
+        return int(w.value), int(t.value)
+
+    def _check_status(self, st):
+        if st != QP_OK:
+            raise QPError(st, LIB.qp_batch_last_error(self.h).decode())
 
     def solve(self, opts: Optional[IpmOptions] = None, workgroups: int = 0):
         if opts is None:

@@ -88,3 +88,46 @@ def test_batch_rejects_unsupported_inputs():
     with pytest.raises(QPError) as e:
         QPBatch([W.rt_qp(5, 100, 10, 0.1, 5)])
     assert e.value.status == QP_ERR_UNSUPPORTED
+
+
+def test_teams_of_workgroups_match_one_workgroup_per_instance_and_the_oracle():
+    """Teams of 2, 4 and 8 workgroups (and teams of one beside them, each size
+    with its own queue) in one cooperative launch: per instance the same
+    solve as one workgroup per instance to rounding (the teams' reductions
+    add the members' partials in rank order) and the oracle's optimum."""
+    from paper_2308_00637_amd.qpk import QPBatch
+    rng = np.random.default_rng(31)
+    specs = []
+    for i in range(12):
+        n = int(rng.integers(150, 420))
+        specs.append(W.dense_qp(rng, n, int(rng.integers(n, 2 * n + 1)), n // 2, name=f"t{i}"))
+    sizes = [8, 4, 2, 1] * 3
+    qb = QPBatch(specs)
+    solo, st0 = qb.solve()
+    qb.set_teams(sizes)
+    team, st1 = qb.solve()
+    wg, teams = qb.launch_shape()
+    print(f"teams: {wg} workgroups in {teams} teams, {team[0].time_ms:.1f} ms "
+          f"(one workgroup each: {solo[0].time_ms:.1f} ms)", flush=True)
+    assert st0 == 0 and st1 == 0
+    assert 4 <= teams <= wg <= 1024
+    for i, (a, b) in enumerate(zip(team, solo)):
+        rel = abs(a.objective - b.objective) / max(1.0, abs(b.objective))
+        print(f"  {i}: n={specs[i].n} team {sizes[i]}: ipm {a.iterations}/{b.iterations} "
+              f"cg {a.total_cg_iters}/{b.total_cg_iters} obj rel {rel:.1e}", flush=True)
+        assert a.result == 0 and abs(a.iterations - b.iterations) <= 1
+        assert rel <= 1e-9
+    check(specs, team, qb)
+
+
+def test_team_sizes_are_checked():
+    from paper_2308_00637_amd.qpk import QPBatch, QPError, QP_ERR_ARG
+    qb = QPBatch([W.tiny_dense(0)])
+    for bad in ([3], [0], [128]):
+        with pytest.raises(QPError) as e:
+            qb.set_teams(bad)
+        assert e.value.status == QP_ERR_ARG
+    qb.set_teams([64])
+    infos, st = qb.solve()
+    assert st == 0 and infos[0].result == 0
+    assert qb.launch_shape() == (64, 1)
