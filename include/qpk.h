@@ -347,6 +347,23 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
  * reported as QP_ERR_HIP rather than waited for.  qp_batch_launch_shape
  * returns the last launch's workgroups and teams (HOST outs, may be NULL). */
 qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size);
+/* Sets team sizes from measured times (then as qp_batch_set_teams).  The
+ * instances are classed by precision, H kind and the binary order of
+ * magnitude of the bytes one PCG iteration reads; each class's largest
+ * instance is timed alone with teams of 1, 2, 4, ... up to max_team (<= 0:
+ * 64) workgroups (one IPM iteration of at most 24 PCG iterations; the
+ * instance's iterate is overwritten, a later solve starts afresh).  The
+ * times are appended to the text table at table_path (HOST string, may be
+ * NULL: nothing read or kept), one line per measurement: device
+ * architecture, float32 storage (0/1), H kind, class, team size,
+ * microseconds per PCG iteration; measurements found there are not taken
+ * again.  Starting from teams of one, the instance with the longest PCG
+ * iteration gets twice the team while that lowers the estimated makespan
+ * (the larger of the slowest iteration and the total workgroup time over the
+ * co-resident workgroups).  HOST outs, may be NULL: team_out (one per
+ * instance), probes_out (measurements taken by this call). */
+qp_status qp_batch_autotune(qp_batch b, const char* table_path, int32_t max_team, int32_t* team_out,
+                            int32_t* probes_out);
 qp_status qp_batch_launch_shape(qp_batch b, int32_t* workgroups, int32_t* teams);
 qp_status qp_batch_get_solution(qp_batch b, int32_t i, double* x, double* lam, double* s);
 const char* qp_batch_last_error(qp_batch b);

@@ -21,6 +21,7 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -1160,6 +1161,205 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
   }
   if (worst != QP_OK) b->err = "at least one instance stopped on a numerical error (see its info)";
   return worst;
+}
+
+// ------------------------------------------------------------ autotuner
+// Team sizes chosen from measured times.  Instances fall into classes by
+// operator precision, H kind and the binary order of magnitude of the bytes
+// one PCG iteration reads (2mn + n^2 or 2mn + 2nk values).  For each class
+// its largest instance is timed alone with teams of 1, 2, 4, ... workgroups:
+// one IPM iteration capped at kProbeIters PCG iterations, the time per PCG
+// iteration taken from events around the launch.  The measurements are kept
+// in a text table (one line per measurement: device architecture, precision,
+// H kind, class, team size, microseconds per PCG iteration) that later calls
+// read instead of timing again.  Then, starting from teams of one, the
+// instance whose iteration takes longest gets twice the team while that
+// lowers the estimated makespan: the larger of the slowest instance's
+// iteration time and the total workgroup time over the workgroups that fit.
+constexpr int kProbeIters = 24;
+
+struct TuneKey {
+  std::string arch;
+  int f32, hkind, cls;
+  bool operator==(const TuneKey& o) const {
+    return arch == o.arch && f32 == o.f32 && hkind == o.hkind && cls == o.cls;
+  }
+};
+
+static int tune_class(const BInst& I) {
+  const double bytes = inst_work(I);
+  return std::max(0, (int)std::floor(std::log2(std::max(bytes, 1.0))));
+}
+
+// Times one instance alone with one team of g workgroups; us per PCG iteration.
+static qp_status probe_team(qp_batch b, int id, int g, const BOpts& bo, double* us) {
+  std::vector<int32_t> blob;
+  for (int r = 0; r < g; ++r) blob.push_back(0);               // team_of
+  const int64_t o_first = (int64_t)blob.size(); blob.push_back(0);
+  const int64_t o_size = (int64_t)blob.size(); blob.push_back(g);
+  const int64_t o_queue = (int64_t)blob.size(); blob.push_back(0);
+  const int64_t o_qstart = (int64_t)blob.size(); blob.push_back(0);
+  const int64_t o_qcount = (int64_t)blob.size(); blob.push_back(1);
+  const int64_t o_qnext = (int64_t)blob.size(); blob.push_back(0);
+  const int64_t o_qorder = (int64_t)blob.size(); blob.push_back(id);
+  const int64_t o_abort = (int64_t)blob.size(); blob.push_back(0);
+  if ((int64_t)blob.size() > b->plan_cap) {
+    if (b->d_plan) (void)hipFree(b->d_plan);
+    b->d_plan = nullptr;
+    b->plan_cap = 0;
+    BCHK(hipMalloc((void**)&b->d_plan, sizeof(int32_t) * blob.size()));
+    b->plan_cap = (int64_t)blob.size();
+  }
+  if (b->sync_cap < 1) {
+    BCHK(hipMalloc((void**)&b->d_sync, sizeof(TeamSync)));
+    b->sync_cap = 1;
+  }
+  BCHK(hipMemcpyAsync(b->d_plan, blob.data(), sizeof(int32_t) * blob.size(), hipMemcpyHostToDevice, b->st));
+  BCHK(hipMemsetAsync(b->d_sync, 0, sizeof(TeamSync), b->st));
+  int32_t* P = b->d_plan;
+  TeamPlan plan{};
+  plan.team_of = P; plan.first = P + o_first; plan.size = P + o_size; plan.queue = P + o_queue;
+  plan.qstart = P + o_qstart; plan.qcount = P + o_qcount; plan.qnext = P + o_qnext;
+  plan.qorder = P + o_qorder; plan.sync = b->d_sync; plan.abort = P + o_abort; plan.spin_max = 1 << 26;
+  hipEvent_t e0, e1;
+  BCHK(hipEventCreate(&e0));
+  BCHK(hipEventCreate(&e1));
+  BCHK(hipEventRecord(e0, b->st));
+  auto go = [&](auto* tag) -> hipError_t {
+    using T = std::remove_pointer_t<decltype(tag)>;
+    BArgs<T> a{b->d_inst, b->d_order, b->count, b->d_next, b->d_vec, b->d_out, bo, plan};
+    void* args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_ipm<T>), dim3(g), dim3(kBB),
+                                      args, 0, b->st);
+  };
+  BCHK(b->f32 ? go((float*)nullptr) : go((double*)nullptr));
+  BCHK(hipEventRecord(e1, b->st));
+  BResult r{};
+  BCHK(hipMemcpyAsync(&r, b->d_out + id, sizeof(BResult), hipMemcpyDeviceToHost, b->st));
+  BCHK(hipStreamSynchronize(b->st));
+  float ms = 0.f;
+  BCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1e3 * ms / std::max<int64_t>(1, r.total_cg);
+  return QP_OK;
+}
+
+qp_status qp_batch_autotune(qp_batch b, const char* table_path, int32_t max_team, int32_t* team_out,
+                            int32_t* probes_out) {
+  if (!b) return QP_ERR_ARG;
+  int cap = 0;
+  qp_status cs = coresident(b, &cap);
+  if (cs != QP_OK) return cs;
+  int gmax = max_team > 0 ? std::min(max_team, kTeamMax) : kTeamMax;
+  gmax = std::min(gmax, cap);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  BCHK(hipGetDevice(&dev));
+  BCHK(hipGetDeviceProperties(&prop, dev));
+  std::string arch = prop.gcnArchName;
+  for (char& ch : arch) if (ch == ' ') ch = '_';
+  // the table: key -> (team size -> us per PCG iteration)
+  std::vector<std::pair<TuneKey, std::vector<std::pair<int, double>>>> table;
+  auto find = [&](const TuneKey& k) -> std::vector<std::pair<int, double>>* {
+    for (auto& e : table) if (e.first == k) return &e.second;
+    return nullptr;
+  };
+  if (table_path) {
+    if (FILE* f = std::fopen(table_path, "r")) {
+      char a[256];
+      int f32, hk, cl, g;
+      double us;
+      while (std::fscanf(f, "%255s %d %d %d %d %lf", a, &f32, &hk, &cl, &g, &us) == 6) {
+        TuneKey k{a, f32, hk, cl};
+        auto* v = find(k);
+        if (!v) { table.push_back({k, {}}); v = &table.back().second; }
+        v->push_back({g, us});
+      }
+      std::fclose(f);
+    }
+  }
+  BOpts bo{};
+  bo.gamma = 0.99; bo.mu0 = 1.0; bo.mu_tol = 1e-6; bo.mu_div = 10.0; bo.max_iter = 1;
+  bo.cg_tol = 1e-300; bo.cg_maxit = kProbeIters;
+  // representative (largest) instance per class
+  std::vector<int> cls(b->count);
+  std::vector<std::pair<TuneKey, int>> reps;
+  for (int i = 0; i < b->count; ++i) {
+    cls[i] = tune_class(b->inst[i]);
+    TuneKey k{arch, b->f32 ? 1 : 0, b->inst[i].hkind, cls[i]};
+    bool seen = false;
+    for (auto& r : reps)
+      if (r.first == k) {
+        seen = true;
+        if (inst_work(b->inst[i]) > inst_work(b->inst[r.second])) r.second = i;
+      }
+    if (!seen) reps.push_back({k, i});
+  }
+  int probes = 0;
+  std::vector<std::pair<TuneKey, std::pair<int, double>>> fresh;
+  for (auto& r : reps) {
+    auto* v = find(r.first);
+    if (!v) { table.push_back({r.first, {}}); v = &table.back().second; }
+    for (int g = 1; g <= gmax; g *= 2) {
+      bool have = false;
+      for (auto& m : *v) have = have || m.first == g;
+      if (have) continue;
+      double us = 0.0;
+      cs = probe_team(b, r.second, g, bo, &us);
+      if (cs != QP_OK) return cs;
+      ++probes;
+      v->push_back({g, us});
+      fresh.push_back({r.first, {g, us}});
+    }
+  }
+  if (table_path && !fresh.empty()) {
+    if (FILE* f = std::fopen(table_path, "a")) {
+      for (auto& e : fresh)
+        std::fprintf(f, "%s %d %d %d %d %.6g\n", e.first.arch.c_str(), e.first.f32, e.first.hkind,
+                     e.first.cls, e.second.first, e.second.second);
+      std::fclose(f);
+    }
+  }
+  // greedy doubling against the estimated makespan
+  auto t_of = [&](int i, int g) -> double {
+    TuneKey k{arch, b->f32 ? 1 : 0, b->inst[i].hkind, cls[i]};
+    const auto* v = find(k);
+    // scale the class's time by this instance's share of its representative's work
+    int rep = i;
+    for (auto& r : reps) if (r.first == k) rep = r.second;
+    const double scale = inst_work(b->inst[i]) / std::max(inst_work(b->inst[rep]), 1e-300);
+    for (auto& m : *v) if (m.first == g) return m.second * scale;
+    return INFINITY;
+  };
+  std::vector<int32_t> team(b->count, 1);
+  auto makespan = [&]() {
+    double slow = 0.0, total = 0.0;
+    for (int i = 0; i < b->count; ++i) {
+      const double t = t_of(i, team[i]);
+      slow = std::max(slow, t);
+      total += t * team[i];
+    }
+    return std::max(slow, total / cap);
+  };
+  double cur = makespan();
+  for (;;) {
+    int worst = -1;
+    double tw = -1.0;
+    for (int i = 0; i < b->count; ++i) {
+      const double t = t_of(i, team[i]);
+      if (t > tw) { tw = t; worst = i; }
+    }
+    if (worst < 0 || team[worst] * 2 > gmax) break;
+    team[worst] *= 2;
+    const double next = makespan();
+    if (!(next < cur)) { team[worst] /= 2; break; }
+    cur = next;
+  }
+  b->team = team;
+  if (team_out) std::copy(team.begin(), team.end(), team_out);
+  if (probes_out) *probes_out = probes;
+  return QP_OK;
 }
 
 qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size) {

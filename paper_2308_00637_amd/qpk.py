@@ -89,6 +89,7 @@ EXPORTS = [
     "qp_update_data", "qp_fused_layout",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
     "qp_batch_last_error", "ipm_solve_dense_noalloc", "qp_batch_set_teams", "qp_batch_launch_shape",
+    "qp_batch_autotune",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate", "fused")
 
@@ -133,6 +134,7 @@ def _load():
         "qp_batch_last_error": (C.c_char_p, [vp]),
         "qp_batch_set_teams": (C.c_int, [vp, _i32p]),
         "qp_batch_launch_shape": (C.c_int, [vp, _i32p, _i32p]),
+        "qp_batch_autotune": (C.c_int, [vp, C.c_char_p, C.c_int32, _i32p, _i32p]),
         "ipm_solve_dense_noalloc": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
                                               C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo), vp]),
     }
@@ -468,6 +470,15 @@ class QPBatch:
         st = LIB.qp_batch_set_teams(self.h, arr)
         if st != QP_OK:
             raise QPError(st, LIB.qp_batch_last_error(self.h).decode())
+
+    def autotune(self, table_path=None, max_team: int = 0):
+        """Team sizes from measured times (see qp_batch_autotune); returns
+        (team sizes, measurements taken)."""
+        out = (C.c_int32 * len(self.specs))()
+        probes = C.c_int32()
+        path = None if table_path is None else str(table_path).encode()
+        self._check_status(LIB.qp_batch_autotune(self.h, path, int(max_team), out, C.byref(probes)))
+        return [int(v) for v in out], int(probes.value)
 
     def launch_shape(self):
         """(workgroups, teams) of the last solve's launch."""

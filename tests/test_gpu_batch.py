@@ -131,3 +131,34 @@ def test_team_sizes_are_checked():
     infos, st = qb.solve()
     assert st == 0 and infos[0].result == 0
     assert qb.launch_shape() == (64, 1)
+
+
+def test_autotune_picks_teams_from_measurements_and_reuses_its_table(tmp_path):
+    """qp_batch_autotune times each size class's largest instance with teams
+    of 1, 2, 4, ... workgroups, keeps the times in a table and gives the
+    largest instances the largest teams; a second batch with the same
+    classes reads the table and measures nothing.  A bounded solve with the
+    tuned teams agrees with one workgroup per instance to the PCG tolerance
+    (1e-7: the two add their partial sums in different orders)."""
+    from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options
+    rng = np.random.default_rng(41)
+    specs = [W.dense_qp(rng, n, int(1.5 * n), n // 2, name=f"a{n}")
+             for n in (1500, 900, 400, 150, 150, 150)]
+    table = tmp_path / "teams.txt"
+    qb = QPBatch(specs)
+    sizes, probes = qb.autotune(table)
+    lines = table.read_text().splitlines()
+    print(f"tuned team sizes {sizes} after {probes} measurements:\n" + "\n".join(lines), flush=True)
+    assert probes >= 4 and len(lines) == probes
+    assert sizes[0] == max(sizes) and sizes[0] >= 4 and sizes[3] <= sizes[0]
+    sizes2, probes2 = QPBatch(specs).autotune(table)
+    assert probes2 == 0 and sizes2 == sizes
+    o = default_ipm_options(max_iter=3)
+    tuned, st = qb.solve(o)
+    qb.set_teams(None)
+    solo, st0 = qb.solve(o)
+    assert st == 0 and st0 == 0
+    for a, b in zip(tuned, solo):
+        assert a.iterations == b.iterations == 3
+        assert a.rnorm == pytest.approx(b.rnorm, rel=1e-5)
+        assert a.objective == pytest.approx(b.objective, rel=1e-6)
