@@ -45,7 +45,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rt_full",
-                    choices=["rt_full", "rt_small", "svm_full", "svm_rbf", "qn_rt", "tiny_dense"])
+                    choices=["rt_full", "rt_small", "svm_full", "svm_rbf", "qn_rt", "tiny_dense",
+                             "batch3"])
+    ap.add_argument("--batch-take", type=int, default=32,
+                    help="batch3: instances of the 256-instance uneven batch, spread over its sizes")
+    ap.add_argument("--batch-cg", type=int, default=40,
+                    help="batch3: PCG iterations of the first Newton system timed per instance")
+    ap.add_argument("--tune-table", default="",
+                    help="batch3: team-size table of the autotuner (default: a file in the temp dir)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16", "fp32x64", "bf16x64"])
     ap.add_argument("--mu-rule", default="paper", choices=["paper", "mehrotra"],
                     help="the barrier parameter's rule: Algorithm 1's (default) or Mehrotra's "
@@ -402,6 +409,9 @@ def main():
         print("bench.py measures one GPU only: this method's solve runs on a single "
               "MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch3":
+        bench_batch(args)
+        return
     import numpy as np
     import torch
     from paper_2308_00637_amd.qpk import QP, default_ipm_options
@@ -532,6 +542,77 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(spec, args.cpu_iters)
+    print(json.dumps(result), flush=True)
+
+
+def bench_batch(args):
+    """Batched PCG throughput at the uneven batch's shapes (256 dense QPs,
+    n ~ U{500..8000}, m ~ U{n..2n}, G of n/2 x n, float32 storage): a stratified
+    subset of them, each running one IPM iteration whose PCG is held to
+    --batch-cg iterations (a whole solve of this batch takes hundreds of
+    thousands of PCG iterations per instance), once with one workgroup per
+    instance and once with the autotuner's teams.  `value` is PCG iterations
+    per second over the batch with the teams; the bytes are each instance's
+    operator per PCG iteration (A twice, U twice, float32)."""
+    import tempfile
+    import torch
+    from paper_2308_00637_amd import workloads as W
+    from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options, default_pcg_options
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    specs = W.batch_stratified(3, 256, args.batch_take)
+    print(f"[bench] {len(specs)} instances generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    qb = QPBatch(specs, precision="fp32")
+    opts = default_ipm_options(max_iter=1, pcg=default_pcg_options(tol=1e-300, maxit=args.batch_cg))
+    per_it = [4 * (2 * sp.m * sp.n + 2 * sp.n * sp.U.shape[1]) for sp in specs]
+
+    def run(label):
+        infos, st = qb.solve(opts)
+        if st != 0:
+            raise RuntimeError(f"batched solve returned {st}")
+        ms = infos[0].time_ms
+        cg = sum(f.total_cg_iters for f in infos)
+        byts = sum(b * f.total_cg_iters for b, f in zip(per_it, infos))
+        wg, teams = qb.launch_shape()
+        print(f"[bench] {label}: {wg} workgroups, {teams} teams, {ms:.1f} ms, {cg} PCG iterations",
+              file=sys.stderr, flush=True)
+        return {"ms": ms, "pcg_iterations": cg, "pcg_iters_per_s": cg / (ms / 1e3),
+                "GBs": byts / (ms / 1e3) / 1e9, "workgroups": wg, "teams": teams}
+
+    run("warm-up, one workgroup per instance")
+    solo = run("one workgroup per instance")
+    table = args.tune_table or os.path.join(tempfile.gettempdir(), "qpk_team_table.txt")
+    t0 = time.perf_counter()
+    sizes, probes = qb.autotune(table)
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] autotune: {probes} measurements in {tune_s:.1f}s, team sizes {sizes}",
+          file=sys.stderr, flush=True)
+    run("warm-up, teams")
+    team = run("teams")
+    achieved = team["GBs"]
+    result = {
+        "metric": "batched PCG iterations/s at the uneven batch's shapes; achieved HBM GB/s vs peak",
+        "value": team["pcg_iters_per_s"],
+        "unit": "PCG iters/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": team["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 operator / f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch_stratified_{len(specs)}_of_256", "n": [sp.n for sp in specs],
+                   "m": [sp.m for sp in specs], "pcg_iterations_per_instance": args.batch_cg},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_sweep": sum(per_it)},
+        "teams": {"sizes": sizes, "measurements": probes, "autotune_s": tune_s, **team},
+        "one_workgroup_per_instance": solo,
+    }
     print(json.dumps(result), flush=True)
 
 

@@ -232,6 +232,22 @@ def batch_qps(seed: int = 3, count: int = 256, nmin: int = 500, nmax: int = 8000
             for i, (n, m, r) in enumerate(batch_sizes(seed, count, nmin, nmax))]
 
 
+def batch_stratified(seed: int = 3, count: int = 256, take: int = 32, nmin: int = 500,
+                     nmax: int = 8000, strata=None):
+    """`take` instances of the uneven batch above, spread evenly over its
+    sizes: the batch's instances ranked by n, every (count / take)-th rank
+    from the middle of each stratum; each is generated exactly as in the
+    whole batch (same child seed).  `strata`: only these strata (0 = the
+    smallest n)."""
+    sizes = batch_sizes(seed, count, nmin, nmax)
+    ranked = sorted(range(count), key=lambda i: (sizes[i][0], i))
+    step = count / take
+    ks = range(take) if strata is None else strata
+    picks = sorted(ranked[int((k + 0.5) * step)] for k in ks)
+    return [dense_qp(sizes[i][2], sizes[i][0], sizes[i][1], sizes[i][0] // 2, round_f32=True,
+                     name=f"batch{i}_n{sizes[i][0]}_m{sizes[i][1]}") for i in picks]
+
+
 def _csr_from_lengths(rng: np.random.Generator, lengths, ncols: int, col_hi: int) -> sp.csr_matrix:
     """CSR whose row i has lengths[i] distinct uniform columns in [0, col_hi),
     values exp(N(-3, 1))."""

@@ -162,3 +162,39 @@ def test_autotune_picks_teams_from_measurements_and_reuses_its_table(tmp_path):
         assert a.iterations == b.iterations == 3
         assert a.rnorm == pytest.approx(b.rnorm, rel=1e-5)
         assert a.objective == pytest.approx(b.objective, rel=1e-6)
+
+
+def test_uneven_batch_shapes_first_iteration_against_oracle_pcg():
+    """Instances of the 256-instance uneven batch at their real shapes (the
+    three smallest of 32 strata, n from 627 to 1,159) in teams of 1, 4 and
+    16 workgroups: one IPM iteration whose PCG runs 30 iterations, against
+    the oracle's step driven by its own Jacobi PCG for 30 iterations.  The
+    data are float32 values, stored as such on the GPU and summed in float64
+    on both sides."""
+    from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options, default_pcg_options
+    from oracle.pcg import pcg
+    specs = W.batch_stratified(3, 256, 32, strata=[0, 1, 2])
+    qb = QPBatch(specs, precision="fp32")
+    qb.set_teams([1, 4, 16])
+    opts = default_ipm_options(max_iter=1, pcg=default_pcg_options(tol=1e-300, maxit=30))
+    infos, st = qb.solve(opts)
+    assert st == 0
+
+    def direction(prob, st_, mu, res):
+        rhs, _ = O.newton_rhs_doubly(prob, st_, mu)
+        dg = O.jacobi_diagonal(prob, st_, mu)
+        sol, _, _, _ = pcg(lambda v: O.kkt_matvec(prob, st_, mu, v), rhs, dg, tol=1e-300, maxit=30)
+        return O.direction_from_solution(prob, st_, res, sol)
+
+    for i, sp in enumerate(specs):
+        prob = O.from_spec(sp)
+        ref = O.solve(prob, O.IPMOptions(max_iter=1), direction=direction)
+        x, lam, s = qb.solution(i)
+        gst = from_masked(prob, x.cpu().numpy(), lam.cpu().numpy(), s.cpu().numpy())
+        ex = np.max(np.abs(gst.x - ref.state.x)) / max(1.0, np.max(np.abs(ref.state.x)))
+        es = np.max(np.abs(gst.s_lA - ref.state.s_lA)) / max(1.0, np.max(np.abs(ref.state.s_lA)))
+        print(f"n={sp.n} m={sp.m}: cg {infos[i].total_cg_iters}, x {ex:.1e}, s {es:.1e}, "
+              f"rnorm {infos[i].rnorm:.6g} / {ref.log[0]['rnorm']:.6g}", flush=True)
+        assert infos[i].total_cg_iters == 30
+        assert ex <= 1e-8 and es <= 1e-8
+        assert infos[i].rnorm == pytest.approx(ref.log[0]["rnorm"], rel=1e-8)
