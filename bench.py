@@ -434,8 +434,6 @@ def main():
             inf = out["info"]
             print(f"[bench] warmup {w}: ipm={inf.iterations} cg={inf.total_cg_iters} "
                   f"{inf.time_ms / 1e3:.2f}s", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        qp.profile_begin(args.profile_cap, args.profile_every)
         infos = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -446,7 +444,17 @@ def main():
                   f"{out['info'].time_ms / 1e3:.2f}s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        graph = qp.graph_stats()
+        # one more solve with a sample of dispatches timed by events, for the
+        # per-kernel figures (the timed steps above replay their PCG chunks
+        # from a graph, which event-timed launches cannot join)
+        qp.profile_begin(args.profile_cap, args.profile_every)
+        pout = qp.solve(opts, want_state=False)
+        torch.cuda.synchronize()
         prof = qp.profile_end()
+        prof_cg = pout["info"].total_cg_iters
+        print(f"[bench] profiled solve: ipm={pout['info'].iterations} cg={prof_cg} "
+              f"{pout['info'].time_ms / 1e3:.2f}s", file=sys.stderr, flush=True)
         ob = qp.operator_bytes()
         lay = qp.operator_layout()
         fz = qp.fused_layout()
@@ -472,7 +480,7 @@ def main():
             # past a converged PCG solve exit at once, so the whole category's
             # time (mean x dispatches) is spread over the real iterations
             avg_s = ms / cnt / 1e3
-            per_it = avg_s * seen / total_cg
+            per_it = avg_s * seen / prof_cg
             by = kernel_bytes(spec, ob, lay, cat, prec_bytes, fz)
             kern[cat] = {"launches_timed": cnt, "dispatches": seen, "dispatch_avg_us": avg_s * 1e6,
                          "avg_us": per_it * 1e6, "bytes": by, "GBs": by / per_it / 1e9}
@@ -533,6 +541,8 @@ def main():
         "layout": lay,
         "fused": fz,
         "copy_calibration_bytes": calib,
+        "pcg_graph": {"captures": graph[0], "replays": graph[1]},
+        "profiled_solve_s": pout["info"].time_ms / 1e3,
         "pcg_kernel_us_per_iteration": per_iter_us,
         "pcg_wall_us_per_iteration": wall_us,
         # the same count over the time inside the PCG solves only (the IPM's

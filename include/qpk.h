@@ -459,6 +459,19 @@ qp_status qp_operator_layout(qp_handle h, int32_t* chunks, int32_t* work_items,
  * HOST outs, any may be NULL: active (1 while products use it), row ranges
  * (block pairs), columns in the first half, stored entries (with the
  * even-length padding), and failed (1 after such a switch). */
+/* PCG iterations replayed from a HIP graph.  Float64 PCG solves (kkt_pcg_solve,
+ * and those of ipm_solve and qp_backward) with an even pcg_options.check_every
+ * queue their iterations in chunks of check_every: the first chunk's launches
+ * (product, update, direction update, each of which reads the stop flag) are
+ * captured once into a graph on a stream of the library's own, and every full
+ * chunk then replays it on the handle's stream.  The graph is captured again
+ * when a pointer, option or mu it was built with changes (each Newton system
+ * with a new mu); it holds kernels only.  Reduced-precision and profiled
+ * solves launch kernel by kernel, and so does every solve with QPK_GRAPH=0 in
+ * the environment when the handle was created.  HOST outs, may be NULL: the
+ * handle's captures and replays so far. */
+qp_status qp_graph_stats(qp_handle h, int64_t* captures, int64_t* replays);
+
 qp_status qp_fused_layout(qp_handle h, int32_t* active, int32_t* ranges, int32_t* half_cols,
                           int64_t* stored, int32_t* failed);
 

@@ -119,7 +119,20 @@ struct qp_handle_s {
     int used[QP_PROF_COUNT] = {};
     int64_t seen[QP_PROF_COUNT] = {};            // dispatches offered so far
   } prof;
+  // A chunk of PCG iterations captured as a HIP graph and replayed (float64
+  // solves without profiling): the key holds what its kernels were built with.
+  struct Graph {
+    bool enabled = true;          // QPK_GRAPH=0: launch kernel by kernel
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap = nullptr;    // capture stream (the handle's may be the null stream)
+    std::vector<uintptr_t> key;
+    int64_t replays = 0, captures = 0;
+  } gr;
   ~qp_handle_s() {
+    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (gr.graph) (void)hipGraphDestroy(gr.graph);
+    if (gr.cap) (void)hipStreamDestroy(gr.cap);
     for (int c = 0; c < QP_PROF_COUNT; ++c)
       for (hipEvent_t e : prof.ev[c]) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -355,10 +368,13 @@ static bool fused_active(qp_handle h) { return h->fz.on && !h->fz.failed; }
 // (PCG iterations only, when pcg_fuses_epilogue): the x-part of y is left as
 // per-chunk partials, and the row pass's partials carry all of p.q.
 static qp_status run_matvec(qp_handle h, bool lo, const double* v, double* y, const int* done,
-                            int* bump, bool fuse = false) {
+                            int* bump, bool fuse = false, int parity = -1) {
   const int vk = lo ? h->vk : VK_F64;
   const bool prof = bump != nullptr;  // only the PCG iteration's own matvec is timed
-  const bool rev = h->alternate && (h->n_matvec++ & 1);
+  // row direction of the blocked passes: by the PCG iteration's parity when
+  // given (the same in a replayed chunk as in launches one by one), else by
+  // the count of products
+  const bool rev = h->alternate && ((parity >= 0 ? parity : h->n_matvec++) & 1);
   if (reinterpret_cast<uintptr_t>(v) & 15) {
     // the blocked row pass stages v with 16-byte loads
     HIPCHK(launch_copy(v, h->valign, h->N(), 1.0, h->st));
@@ -563,6 +579,59 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
     au.coef = h->coef;
   }
   const int check = std::max(1, o.check_every);
+  // One iteration's launches (product, update, direction update): queued
+  // directly or recorded into the chunk graph.
+  auto queue_iteration = [&](int iter) -> qp_status {
+    CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT, fuse, iter));
+    const KEvents e1 = prof_slot(h, QP_PROF_CGUPDATE, true);
+    HIPCHK(launch_cg_update(au, h->st, &e1));
+    const KEvents e2 = prof_slot(h, QP_PROF_CGPUPDATE, true);
+    HIPCHK(launch_cg_pupdate(a, h->st, &e2));
+    return QP_OK;
+  };
+  // Chunks of `check` iterations replay one captured graph: the kernels'
+  // arguments do not change from one chunk to the next (the fused pass's
+  // exchange parity alternates within the chunk, `check` even), and every
+  // kernel reads the stop flag itself.  Reduced-precision solves (residual
+  // replacement between iterations) and profiled solves launch directly.
+  const bool graph = h->gr.enabled && !lo && !h->prof.on && check >= 2 && (check % 2) == 0 &&
+                     o.maxit >= check;
+  if (graph) {
+    // everything a captured kernel takes by value: pointers, options and mu
+    // (the equality rows' penalty of the product)
+    uint64_t mu_bits = 0, tol_bits = 0;
+    std::memcpy(&mu_bits, &h->mu, sizeof(double));
+    std::memcpy(&tol_bits, &o.tol, sizeof(double));
+    const std::vector<uintptr_t> key = {
+        (uintptr_t)rhs, (uintptr_t)sol, (uintptr_t)a.jdiag, (uintptr_t)au.coef, (uintptr_t)check,
+        (uintptr_t)fused, (uintptr_t)fuse, (uintptr_t)tol_bits, (uintptr_t)mu_bits,
+        (uintptr_t)o.maxit, (uintptr_t)h->fz.failed, (uintptr_t)h->alternate};
+    if (!h->gr.exec || h->gr.key != key) {
+      if (h->gr.exec) { (void)hipGraphExecDestroy(h->gr.exec); h->gr.exec = nullptr; }
+      if (h->gr.graph) { (void)hipGraphDestroy(h->gr.graph); h->gr.graph = nullptr; }
+      if (!h->gr.cap) HIPCHK(hipStreamCreateWithFlags(&h->gr.cap, hipStreamNonBlocking));
+      // the launches are recorded on a stream of the handle's own (capture
+      // is not allowed on the null stream); the graph then runs on h->st
+      const hipStream_t user = h->st;
+      h->st = h->gr.cap;
+      hipError_t ec = hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal);
+      qp_status cs = QP_OK;
+      if (ec == hipSuccess)
+        for (int c = 0; c < check && cs == QP_OK; ++c) cs = queue_iteration(c);
+      hipGraph_t g = nullptr;
+      if (ec == hipSuccess) ec = hipStreamEndCapture(h->st, &g);
+      h->st = user;
+      if (cs != QP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return cs;
+      }
+      HIPCHK(ec);
+      h->gr.graph = g;
+      HIPCHK(hipGraphInstantiate(&h->gr.exec, g, nullptr, nullptr, 0));
+      h->gr.key = key;
+      h->gr.captures++;
+    }
+  }
   int it = 0;
   CHK(read_back(h));
   bool done = h->hfl[F_DONE] != 0;
@@ -575,17 +644,17 @@ static qp_status run_pcg(qp_handle h, const double* rhs, double* sol, const pcg_
     bool queued = false;
     while (!done && it < o.maxit) {
       const int chunk = std::min(check, o.maxit - it);
-      for (int c = 0; c < chunk; ++c, ++it) {
+      if (graph && chunk == check) {
+        HIPCHK(hipGraphLaunch(h->gr.exec, h->st));
+        h->gr.replays++;
+        it += chunk;
+      } else for (int c = 0; c < chunk; ++c, ++it) {
         if (lo && o.rr_period > 0 && it > 0 && it % o.rr_period == 0) {
           // residual replacement: r = rhs - K x with the float64 operator
           CHK(run_matvec(h, false, sol, h->tmp, h->fl + F_DONE, nullptr));
           HIPCHK(launch_cg_restart(a, h->tmp, 0, h->st));
         }
-        CHK(run_matvec(h, lo, h->cg_p, h->cg_q, h->fl + F_DONE, h->fl + F_CNT, fuse));
-        const KEvents e1 = prof_slot(h, QP_PROF_CGUPDATE, true);
-        HIPCHK(launch_cg_update(au, h->st, &e1));
-        const KEvents e2 = prof_slot(h, QP_PROF_CGPUPDATE, true);
-        HIPCHK(launch_cg_pupdate(a, h->st, &e2));
+        CHK(queue_iteration(it));
       }
       int* snap = h->hpoll + slot * F_COUNT;
       HIPCHK(hipMemcpyAsync(snap, h->fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, h->st));
@@ -1381,6 +1450,7 @@ static qp_status create_impl(qp_handle h, const qp_desc* d) {
   CHK(dalloc_t(h, &h->cg_r, N));
   CHK(dalloc_t(h, &h->cg_z, N));
   CHK(dalloc_t(h, &h->cg_p, N));
+  if (const char* e = std::getenv("QPK_GRAPH")) h->gr.enabled = std::atoi(e) != 0;
   CHK(dalloc_t(h, &h->cg_q, N));
   CHK(dalloc_t(h, &h->tmp, N));
   CHK(dalloc_t(h, &h->arhs, N));
@@ -1935,6 +2005,13 @@ qp_status qp_operator_bytes(qp_handle h, int64_t* row_bytes, int64_t* col_bytes,
   if (dense_bytes) *dense_bytes = (int64_t)h->n * h->k * vb;
   if (row_nnz) *row_nnz = h->nnz_rp;
   if (col_nnz) *col_nnz = h->nnz_xs;
+  return QP_OK;
+}
+
+qp_status qp_graph_stats(qp_handle h, int64_t* captures, int64_t* replays) {
+  if (!h) return QP_ERR_ARG;
+  if (captures) *captures = h->gr.captures;
+  if (replays) *replays = h->gr.replays;
   return QP_OK;
 }
 

@@ -89,7 +89,7 @@ EXPORTS = [
     "qp_update_data", "qp_fused_layout",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
     "qp_batch_last_error", "ipm_solve_dense_noalloc", "qp_batch_set_teams", "qp_batch_launch_shape",
-    "qp_batch_autotune",
+    "qp_batch_autotune", "qp_graph_stats",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate", "fused")
 
@@ -135,6 +135,7 @@ def _load():
         "qp_batch_set_teams": (C.c_int, [vp, _i32p]),
         "qp_batch_launch_shape": (C.c_int, [vp, _i32p, _i32p]),
         "qp_batch_autotune": (C.c_int, [vp, C.c_char_p, C.c_int32, _i32p, _i32p]),
+        "qp_graph_stats": (C.c_int, [vp, _i64p, _i64p]),
         "ipm_solve_dense_noalloc": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
                                               C.POINTER(IpmOptions), vp, vp, vp, C.POINTER(IpmInfo), vp]),
     }
@@ -410,6 +411,12 @@ class QP:
         self._check(LIB.qp_operator_layout(self.h, *arr))
         return {side: {"chunks": int(arr[0][i]), "work_items": int(arr[1][i]),
                        "chunk_cols": int(arr[2][i])} for i, side in enumerate(("row", "col"))}
+
+    def graph_stats(self):
+        """(captures, replays) of the PCG chunk graph (see qp_graph_stats)."""
+        c, r = C.c_int64(), C.c_int64()
+        self._check(LIB.qp_graph_stats(self.h, C.byref(c), C.byref(r)))
+        return int(c.value), int(r.value)
 
     def fused_layout(self):
         """The fused single-read product: active, row ranges, columns of the
