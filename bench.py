@@ -239,8 +239,8 @@ def kernel_category(lay):
             return "epilogue"
         if name.startswith("k_ts_reduce"):
             return "tsreduce"
-        if name in ("k_cg_update", "k_cg_pupdate"):
-            return name.replace("k_", "")
+        if name in ("k_cg_update", "k_cg_update_split", "k_cg_pupdate"):
+            return "cg_update" if name.startswith("k_cg_update") else "cg_pupdate"
         if name.startswith("k_fused<"):
             return "fused"
         return None
