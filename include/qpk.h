@@ -343,9 +343,12 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
  * above 1, ipm_solve_batch makes one cooperative launch of at most the
  * co-resident workgroups (and at most `workgroups` when positive): each team
  * size gets its own queue of instances and a number of teams in proportion to
- * its instances' work.  A team whose members cannot all be resident is
- * reported as QP_ERR_HIP rather than waited for.  qp_batch_launch_shape
- * returns the last launch's workgroups and teams (HOST outs, may be NULL). */
+ * its instances' work; a team whose queue is empty then takes instances from
+ * the queues of smaller team sizes (which team solves an instance, and so
+ * its rounding, can differ between launches).  A team whose members cannot
+ * all be resident is reported as QP_ERR_HIP rather than waited for.
+ * qp_batch_launch_shape returns the last launch's workgroups and teams (HOST
+ * outs, may be NULL). */
 qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size);
 /* Sets team sizes from measured times (then as qp_batch_set_teams).  The
  * instances are classed by precision, H kind and the binary order of

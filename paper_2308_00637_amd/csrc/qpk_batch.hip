@@ -102,6 +102,7 @@ struct TeamPlan {
   TeamSync* sync;
   int32_t* abort;
   int32_t spin_max;
+  int32_t nqueue;   // queues, by team size, largest first
 };
 
 template <typename T>
@@ -660,16 +661,15 @@ __device__ __forceinline__ void solve_one(Team& tm, const BArgs<T>& a, int id) {
 }
 
 // Every workgroup belongs to a team (of one without a plan); a team draws
-// instances from its queue until the queue is empty.  The team's first
-// member draws and passes the index to the others through the team's state.
+// instances from its queue until the queue is empty, then helps the queues
+// of smaller team sizes (smaller instances) in turn.  The team's first member
+// draws and passes the index to the others through the team's state.
 template <typename T>
 __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
   __shared__ int slot;
   Team tm;
-  const int32_t* order = a.order;
-  int32_t count = a.count;
-  int32_t* next = a.next;
   tm.G = 1; tm.r = 0; tm.ts = nullptr; tm.abort = nullptr; tm.spin_max = 0;
+  int home = 0, nq = 1;
   if (a.plan.team_of) {
     const int t = a.plan.team_of[blockIdx.x];
     tm.G = a.plan.size[t];
@@ -677,27 +677,30 @@ __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
     tm.ts = a.plan.sync + t;
     tm.abort = a.plan.abort;
     tm.spin_max = a.plan.spin_max;
-    const int q = a.plan.queue[t];
-    order = a.plan.qorder + a.plan.qstart[q];
-    count = a.plan.qcount[q];
-    next = a.plan.qnext + q;
+    home = a.plan.queue[t];
+    nq = a.plan.nqueue;
   }
   tm.gen = 0;
   tm.slot = 0;
-  for (;;) {
-    if (tm.r == 0 && threadIdx.x == 0) {
-      slot = atomicAdd(next, 1);
-      if (tm.G > 1) tm.ts->cur = slot;
+  for (int qq = home; qq < nq; ++qq) {
+    const int32_t* order = a.plan.team_of ? a.plan.qorder + a.plan.qstart[qq] : a.order;
+    const int32_t count = a.plan.team_of ? a.plan.qcount[qq] : a.count;
+    int32_t* next = a.plan.team_of ? a.plan.qnext + qq : a.next;
+    for (;;) {
+      if (tm.r == 0 && threadIdx.x == 0) {
+        slot = atomicAdd(next, 1);
+        if (tm.G > 1) tm.ts->cur = slot;
+      }
+      team_sync(tm);
+      if (tm.r != 0 && threadIdx.x == 0) slot = tm.ts->cur;
+      __syncthreads();
+      // the slot is the same for the whole workgroup: make that visible to the
+      // compiler so the instance's sizes and offsets live in scalar registers
+      const int q = __builtin_amdgcn_readfirstlane(slot);
+      __syncthreads();
+      if (q >= count) break;
+      solve_one(tm, a, __builtin_amdgcn_readfirstlane(order[q]));
     }
-    team_sync(tm);
-    if (tm.r != 0 && threadIdx.x == 0) slot = tm.ts->cur;
-    __syncthreads();
-    // the slot is the same for the whole workgroup: make that visible to the
-    // compiler so the instance's sizes and offsets live in scalar registers
-    const int q = __builtin_amdgcn_readfirstlane(slot);
-    __syncthreads();
-    if (q >= count) break;
-    solve_one(tm, a, __builtin_amdgcn_readfirstlane(order[q]));
   }
 }
 
@@ -1040,6 +1043,7 @@ static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
   plan->qnext = P + o_qnext; plan->qorder = P + o_qorder; plan->sync = b->d_sync;
   plan->abort = P + o_abort;
   plan->spin_max = 1 << 26;
+  plan->nqueue = nq;
   *grid = W;
   b->last_grid = W;
   b->last_teams = teams;
@@ -1221,6 +1225,7 @@ static qp_status probe_team(qp_batch b, int id, int g, const BOpts& bo, double* 
   plan.team_of = P; plan.first = P + o_first; plan.size = P + o_size; plan.queue = P + o_queue;
   plan.qstart = P + o_qstart; plan.qcount = P + o_qcount; plan.qnext = P + o_qnext;
   plan.qorder = P + o_qorder; plan.sync = b->d_sync; plan.abort = P + o_abort; plan.spin_max = 1 << 26;
+  plan.nqueue = 1;
   hipEvent_t e0, e1;
   BCHK(hipEventCreate(&e0));
   BCHK(hipEventCreate(&e1));
