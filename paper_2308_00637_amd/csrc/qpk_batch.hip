@@ -22,6 +22,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -88,8 +89,9 @@ struct TeamSync {
 // whose members are workgroups first[t] .. first[t] + size[t] - 1; team t
 // takes instances from queue queue[t], i.e. qorder[qstart[q] + i] for the
 // i it draws from the counter qnext[q] (i < qcount[q]).  A wait at a team
-// barrier gives up after spin_max polls and sets *abort (every later wait
-// then returns at once; the results of that launch are invalid).
+// barrier gives up after spin_max polls and sets *abort; every team that
+// meets a barrier after that leaves its instance and the launch (the results
+// of that launch are invalid), so the grid drains instead of running on.
 struct TeamPlan {
   const int32_t* team_of;
   const int32_t* first;
@@ -131,6 +133,7 @@ struct Team {
   int32_t spin_max;
   unsigned long long gen;   // barriers passed
   int slot;                 // next reduction slot
+  int dead;                 // the launch was aborted: leave at once
   __device__ int tid() const { return r * kBB + static_cast<int>(threadIdx.x); }
   __device__ int nthr() const { return G * kBB; }
   __device__ int wave() const { return r * kBW + static_cast<int>(threadIdx.x >> 6); }
@@ -142,6 +145,7 @@ struct Team {
 // device scope, counts its arrival and waits for the count of this barrier,
 // then acquires; the workgroup's own barrier brackets it.
 __device__ __noinline__ void team_sync(Team& t) {
+  __shared__ int aborted;
   __syncthreads();
   if (t.G == 1) return;
   ++t.gen;
@@ -159,8 +163,10 @@ __device__ __noinline__ void team_sync(Team& t) {
       __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    aborted = __hip_atomic_load(t.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
+  t.dead = aborted;
 }
 
 // Sums (MIN: minima) over the team of NV values per thread, the same bits on
@@ -213,69 +219,169 @@ __device__ __forceinline__ double team_sum(Team& t, double v) {
 
 // Loads in flight per lane in the operator loops below: each batch issues
 // all of its loads before the first product, so a wave waits for one memory
-// latency per batch instead of one per element.  The products are added in
-// the same order as one element at a time.
+// latency per batch instead of one per element.  What is left after the full
+// batches goes in one more batch whose indexes are clamped to the last
+// element (in bounds) and whose products past the end are zeroed, so short
+// rows and columns do not fall back to one latency per element.  The
+// products are added in the same order as one element at a time.
 constexpr int kUnroll = 16;
 
-// out[r] = sum_c M[r][c] * v[c] (SQ: M^2), one wave of the team per row.
+// The operators and vectors live in device memory.  Addressing them as
+// global memory from a wave-uniform base (scalar registers) plus the lane's
+// offset keeps the address arithmetic out of the vector registers and the
+// loads off the counter that LDS and scalar loads share.
+template <typename T>
+using gmem = const __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* as_global(const T* p) {
+  return (gmem<T>*)p;
+}
+
+// out[r] = sum_c M[r][c] * v[c] (SQ: M^2).  Each wave of the team takes
+// kRowB rows at a time and walks them together, kColB columns per lane per
+// batch: kRowB * kColB operator loads in flight per lane, one load of v for
+// all kRowB rows, and a row shorter than a batch still shares its latency
+// with the other rows.
+constexpr int kRowB = 4;
 template <bool SQ, typename T>
-__device__ __forceinline__ void rowdots(const Team& tm, const T* __restrict__ M, int R, int Cn,
+__device__ __noinline__ void rowdots(const Team& tm, const T* __restrict__ M, int R, int Cn,
                                         const double* __restrict__ v, double* __restrict__ out) {
+  constexpr int kColB = sizeof(T) == 4 ? 4 : 2;
   const int lane = threadIdx.x & 63;
-  for (int r = tm.wave(); r < R; r += tm.nwave()) {
-    const T* row = M + static_cast<int64_t>(r) * Cn;
-    double acc = 0.0;
-    int c = lane;
-    for (; c + (kUnroll - 1) * 64 < Cn; c += kUnroll * 64) {
-      T a[kUnroll];
-      double vv[kUnroll];
+  const int wv = __builtin_amdgcn_readfirstlane(tm.wave());
+  const int step = __builtin_amdgcn_readfirstlane(tm.nwave()) * kRowB;
+  for (int r0 = wv * kRowB; r0 < R; r0 += step) {
+    const int nr = min(kRowB, R - r0);
+    double acc[kRowB];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) a[u] = row[c + 64 * u];
+    for (int q = 0; q < kRowB; ++q) acc[q] = 0.0;
+    for (int c0 = 0; c0 < Cn; c0 += kColB * 64) {
+      T a[kRowB][kColB];
+      double vv[kColB];
+      gmem<double>* vb = as_global(v + c0);
+      if (__builtin_amdgcn_readfirstlane(nr == kRowB && c0 + kColB * 64 <= Cn)) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) vv[u] = v[c + 64 * u];
+        for (int u = 0; u < kColB; ++u) vv[u] = vb[lane + 64 * u];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const double d = static_cast<double>(a[u]);
-        acc += (SQ ? d * d : d) * vv[u];
+        for (int q = 0; q < kRowB; ++q) {
+          gmem<T>* rq = as_global(M + static_cast<int64_t>(r0 + q) * Cn + c0);
+#pragma unroll
+          for (int u = 0; u < kColB; ++u) a[q][u] = rq[lane + 64 * u];
+        }
+      } else {
+        // the last batch of a row group: offsets clamped to the last column
+        // and rows to the last row (all in bounds), values outside zeroed
+        const int lim = Cn - 1 - c0;
+        int off[kColB];
+#pragma unroll
+        for (int u = 0; u < kColB; ++u) off[u] = min(lane + 64 * u, lim);
+#pragma unroll
+        for (int u = 0; u < kColB; ++u) vv[u] = vb[off[u]];
+#pragma unroll
+        for (int q = 0; q < kRowB; ++q) {
+          gmem<T>* rq = as_global(M + static_cast<int64_t>(r0 + min(q, nr - 1)) * Cn + c0);
+#pragma unroll
+          for (int u = 0; u < kColB; ++u) a[q][u] = rq[off[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kColB; ++u) {
+          const bool in = lane + 64 * u <= lim;
+          vv[u] = in ? vv[u] : 0.0;
+#pragma unroll
+          for (int q = 0; q < kRowB; ++q) a[q][u] = (in && q < nr) ? a[q][u] : T(0);
+        }
       }
-    }
-    for (; c < Cn; c += 64) {
-      const double a = static_cast<double>(row[c]);
-      acc += (SQ ? a * a : a) * v[c];
+#pragma unroll
+      for (int q = 0; q < kRowB; ++q)
+#pragma unroll
+        for (int u = 0; u < kColB; ++u) {
+          const double d = static_cast<double>(a[q][u]);
+          acc[q] += (SQ ? d * d : d) * vv[u];
+        }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) out[r] = acc;
+    for (int q = 0; q < kRowB; ++q) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
+      if (lane == 0 && q < nr) out[r0 + q] = acc[q];
+    }
   }
 }
 
-// out[c] = sum_r M[r][c] * w[r] (SQ: M^2): 64-column tiles spread over the
-// team's workgroups (so even a team of 64 finds work in an 8,000-column
-// operator), sixteen row groups per tile, combined in LDS in group order.
+// out[c] = sum_r M[r][c] * w[r] (SQ: M^2).  Wide operators (at least 768
+// columns per member of the team): 1024-column tiles, one column per thread,
+// each thread walking all rows in order, so a workgroup reads 4 KB of each
+// of kUnroll consecutive rows per batch (close to a plain stream's rate).
+// Narrow ones: 64-column tiles spread over the team's workgroups (so even a
+// team of 64 finds work), sixteen row groups per tile, combined in LDS in
+// group order.
 constexpr int kTileW = 64, kTileRG = kBB / kTileW;
 template <bool SQ, typename T>
-__device__ __forceinline__ void coldots(const Team& tm, const T* __restrict__ M, int R, int Cn,
-                                        const double* __restrict__ w, double* __restrict__ out) {
-  __shared__ double red[kBB];
-  const int cc = threadIdx.x & (kTileW - 1), rg = threadIdx.x / kTileW;
-  for (int c0 = tm.r * kTileW; c0 < Cn; c0 += kTileW * tm.G) {
-    const int c = c0 + cc;
+__device__ __noinline__ void coldots_wide(const Team& tm, const T* __restrict__ M, int R, int Cn,
+                                          const double* __restrict__ w, double* __restrict__ out) {
+  gmem<double>* wg = as_global(w);
+  for (int c0 = tm.r * kBB; c0 < Cn; c0 += kBB * tm.G) {
+    const int c = c0 + static_cast<int>(threadIdx.x);
+    const int off = min(static_cast<int>(threadIdx.x), Cn - 1 - c0);  // in bounds
     double acc = 0.0;
-    if (c < Cn) {
-      int r = rg;
-      for (; r + kTileRG * (kUnroll - 1) < R; r += kTileRG * kUnroll) {
-        T a[kUnroll];
+    for (int r = 0; r < R; r += kUnroll) {
+      T a[kUnroll];
+      if (r + kUnroll <= R) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) a[u] = M[static_cast<int64_t>(r + kTileRG * u) * Cn + c];
+        for (int u = 0; u < kUnroll; ++u) a[u] = as_global(M + static_cast<int64_t>(r + u) * Cn + c0)[off];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           const double d = static_cast<double>(a[u]);
-          acc += (SQ ? d * d : d) * w[r + kTileRG * u];
+          acc += (SQ ? d * d : d) * wg[r + u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          a[u] = as_global(M + static_cast<int64_t>(min(r + u, R - 1)) * Cn + c0)[off];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double d = r + u < R ? static_cast<double>(a[u]) : 0.0;
+          const double ww = r + u < R ? wg[r + u] : 0.0;
+          acc += (SQ ? d * d : d) * ww;
         }
       }
-      for (; r < R; r += kTileRG) {
-        const double a = static_cast<double>(M[static_cast<int64_t>(r) * Cn + c]);
-        acc += (SQ ? a * a : a) * w[r];
+    }
+    if (c < Cn) out[c] = acc;
+  }
+}
+
+template <bool SQ, typename T>
+__device__ __noinline__ void coldots_tiles(const Team& tm, const T* __restrict__ M, int R, int Cn,
+                                           const double* __restrict__ w, double* __restrict__ out) {
+  __shared__ double red[kBB];
+  gmem<double>* wg = as_global(w);
+  const int cc = threadIdx.x & (kTileW - 1);
+  const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileW);  // one row group per wave
+  for (int c0 = tm.r * kTileW; c0 < Cn; c0 += kTileW * tm.G) {
+    const int c = c0 + cc;
+    const int off = min(cc, Cn - 1 - c0);  // in bounds; the sum of c >= Cn is dropped
+    double acc = 0.0;
+    for (int r = rg; r < R; r += kTileRG * kUnroll) {
+      T a[kUnroll];
+      if (__builtin_amdgcn_readfirstlane(r + kTileRG * (kUnroll - 1) < R)) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          a[u] = as_global(M + static_cast<int64_t>(r + kTileRG * u) * Cn + c0)[off];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double d = static_cast<double>(a[u]);
+          acc += (SQ ? d * d : d) * wg[r + kTileRG * u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          a[u] = as_global(M + static_cast<int64_t>(min(r + kTileRG * u, R - 1)) * Cn + c0)[off];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double d = r + kTileRG * u < R ? static_cast<double>(a[u]) : 0.0;
+          const double ww = r + kTileRG * u < R ? wg[r + kTileRG * u] : 0.0;
+          acc += (SQ ? d * d : d) * ww;
+        }
       }
     }
     red[threadIdx.x] = acc;
@@ -288,6 +394,13 @@ __device__ __forceinline__ void coldots(const Team& tm, const T* __restrict__ M,
     }
     __syncthreads();
   }
+}
+
+template <bool SQ, typename T>
+__device__ __forceinline__ void coldots(const Team& tm, const T* __restrict__ M, int R, int Cn,
+                                        const double* __restrict__ w, double* __restrict__ out) {
+  if (Cn >= 768 * tm.G) coldots_wide<SQ>(tm, M, R, Cn, w, out);
+  else coldots_tiles<SQ>(tm, M, R, Cn, w, out);
 }
 
 template <typename T>
@@ -488,6 +601,7 @@ __device__ __noinline__ int pcg(Team& tm, const BInst* bi, double* vec, double t
     return nb == 0.0 ? 0 : QP_ERR_NUMERIC_CODE;
   }
   for (int k = 0; k < maxit; ++k) {
+    if (tm.dead) return QP_ERR_NUMERIC_CODE;
     const double pq = kkt_apply(tm, I, p, q);
     if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz))
       return (isfinite(pq) && isfinite(rz)) ? QP_ERR_NOT_SPD_CODE : QP_ERR_NUMERIC_CODE;
@@ -609,7 +723,7 @@ __device__ __forceinline__ void solve_one(Team& tm, const BArgs<T>& a, int id) {
   int it = 0, status = QP_IPM_MAX_ITER, hits = 0;
   int64_t total = 0;
   const BInst* bi = a.inst + id;
-  for (it = 1; it <= o.max_iter; ++it) {
+  for (it = 1; it <= o.max_iter && !tm.dead; ++it) {
     residuals<T>(tm, bi, a.vec, mu, nrm);
     newton_system<T>(tm, bi, a.vec, mu);
     int conv = 0;
@@ -668,7 +782,7 @@ template <typename T>
 __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
   __shared__ int slot;
   Team tm;
-  tm.G = 1; tm.r = 0; tm.ts = nullptr; tm.abort = nullptr; tm.spin_max = 0;
+  tm.G = 1; tm.r = 0; tm.ts = nullptr; tm.abort = nullptr; tm.spin_max = 0; tm.dead = 0;
   int home = 0, nq = 1;
   if (a.plan.team_of) {
     const int t = a.plan.team_of[blockIdx.x];
@@ -682,7 +796,7 @@ __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
   }
   tm.gen = 0;
   tm.slot = 0;
-  for (int qq = home; qq < nq; ++qq) {
+  for (int qq = home; qq < nq && !tm.dead; ++qq) {
     const int32_t* order = a.plan.team_of ? a.plan.qorder + a.plan.qstart[qq] : a.order;
     const int32_t count = a.plan.team_of ? a.plan.qcount[qq] : a.count;
     int32_t* next = a.plan.team_of ? a.plan.qnext + qq : a.next;
@@ -698,7 +812,7 @@ __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
       // compiler so the instance's sizes and offsets live in scalar registers
       const int q = __builtin_amdgcn_readfirstlane(slot);
       __syncthreads();
-      if (q >= count) break;
+      if (q >= count || tm.dead) break;
       solve_one(tm, a, __builtin_amdgcn_readfirstlane(order[q]));
     }
   }
@@ -947,6 +1061,15 @@ static qp_status coresident(qp_batch b, int* out) {
 // Plans a team launch on at most `cap` workgroups: the instances of each team
 // size form a queue (largest work first); each size gets workgroups in
 // proportion to its instances' work, as whole teams (at least one).
+// Polls of a team barrier before it gives up (about 1 us each: a member
+// lags its team by at most one phase of one instance, milliseconds).
+// QPK_BATCH_SPIN overrides it (at least 1), so tests can force the give-up.
+static int32_t team_spin_limit() {
+  int32_t lim = 1 << 23;
+  if (const char* e = std::getenv("QPK_BATCH_SPIN")) lim = std::max(1, std::atoi(e));
+  return lim;
+}
+
 static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
   std::vector<int> sizes;
   for (int g : b->team) if (std::find(sizes.begin(), sizes.end(), g) == sizes.end()) sizes.push_back(g);
@@ -1042,7 +1165,7 @@ static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
   plan->queue = P + o_queue; plan->qstart = P + o_qstart; plan->qcount = P + o_qcount;
   plan->qnext = P + o_qnext; plan->qorder = P + o_qorder; plan->sync = b->d_sync;
   plan->abort = P + o_abort;
-  plan->spin_max = 1 << 26;
+  plan->spin_max = team_spin_limit();
   plan->nqueue = nq;
   *grid = W;
   b->last_grid = W;
@@ -1224,7 +1347,8 @@ static qp_status probe_team(qp_batch b, int id, int g, const BOpts& bo, double* 
   TeamPlan plan{};
   plan.team_of = P; plan.first = P + o_first; plan.size = P + o_size; plan.queue = P + o_queue;
   plan.qstart = P + o_qstart; plan.qcount = P + o_qcount; plan.qnext = P + o_qnext;
-  plan.qorder = P + o_qorder; plan.sync = b->d_sync; plan.abort = P + o_abort; plan.spin_max = 1 << 26;
+  plan.qorder = P + o_qorder; plan.sync = b->d_sync; plan.abort = P + o_abort;
+  plan.spin_max = team_spin_limit();
   plan.nqueue = 1;
   hipEvent_t e0, e1;
   BCHK(hipEventCreate(&e0));

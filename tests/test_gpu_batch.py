@@ -120,6 +120,35 @@ def test_teams_of_workgroups_match_one_workgroup_per_instance_and_the_oracle():
     check(specs, team, qb)
 
 
+def test_team_barrier_give_up_is_reported_and_the_next_launch_is_clean(monkeypatch):
+    """A barrier spin limit of one poll (set from the host) makes the team
+    barriers give up: the launch drains at once and reports QP_ERR_HIP
+    instead of running on; the next launch with the normal limit solves the
+    same batch as one workgroup per instance."""
+    import time
+    from paper_2308_00637_amd.qpk import QPBatch, QPError, QP_ERR_HIP
+    rng = np.random.default_rng(7)
+    specs = [W.dense_qp(rng, n, n + 40, n // 2, name=f"g{n}") for n in (220, 180, 150)]
+    qb = QPBatch(specs)
+    solo, st0 = qb.solve()
+    assert st0 == 0
+    qb.set_teams([4, 2, 1])
+    monkeypatch.setenv("QPK_BATCH_SPIN", "1")
+    t0 = time.perf_counter()
+    with pytest.raises(QPError) as e:
+        qb.solve()
+    took = time.perf_counter() - t0
+    print(f"forced give-up reported in {took:.2f} s: {e.value}", flush=True)
+    assert e.value.status == QP_ERR_HIP
+    assert took < 20.0
+    monkeypatch.delenv("QPK_BATCH_SPIN")
+    team, st1 = qb.solve()
+    assert st1 == 0
+    for a, b in zip(team, solo):
+        assert a.result == 0 and abs(a.iterations - b.iterations) <= 1
+        assert abs(a.objective - b.objective) <= 1e-9 * max(1.0, abs(b.objective))
+
+
 def test_team_sizes_are_checked():
     from paper_2308_00637_amd.qpk import QPBatch, QPError, QP_ERR_ARG
     qb = QPBatch([W.tiny_dense(0)])
@@ -138,8 +167,11 @@ def test_autotune_picks_teams_from_measurements_and_reuses_its_table(tmp_path):
     of 1, 2, 4, ... workgroups, keeps the times in a table and gives the
     largest instances the largest teams; a second batch with the same
     classes reads the table and measures nothing.  A bounded solve with the
-    tuned teams agrees with one workgroup per instance to the PCG tolerance
-    (1e-7: the two add their partial sums in different orders)."""
+    tuned teams agrees with one workgroup per instance to what the PCG
+    tolerance allows after three IPM steps (each Newton system solved to a
+    relative residual of 1e-7, the two adding their partial sums in
+    different orders: the large instance's column products walk all rows in
+    one sum on one workgroup and sixteen row groups per tile on a team)."""
     from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options
     rng = np.random.default_rng(41)
     specs = [W.dense_qp(rng, n, int(1.5 * n), n // 2, name=f"a{n}")
@@ -161,21 +193,23 @@ def test_autotune_picks_teams_from_measurements_and_reuses_its_table(tmp_path):
     for a, b in zip(tuned, solo):
         assert a.iterations == b.iterations == 3
         assert a.rnorm == pytest.approx(b.rnorm, rel=1e-5)
-        assert a.objective == pytest.approx(b.objective, rel=1e-6)
+        assert a.objective == pytest.approx(b.objective, rel=1e-5)
 
 
-def test_uneven_batch_shapes_first_iteration_against_oracle_pcg():
+@pytest.mark.parametrize("teams", [[1, 4, 16], None])
+def test_uneven_batch_shapes_first_iteration_against_oracle_pcg(teams):
     """Instances of the 256-instance uneven batch at their real shapes (the
     three smallest of 32 strata, n from 627 to 1,159) in teams of 1, 4 and
-    16 workgroups: one IPM iteration whose PCG runs 30 iterations, against
-    the oracle's step driven by its own Jacobi PCG for 30 iterations.  The
-    data are float32 values, stored as such on the GPU and summed in float64
-    on both sides."""
+    16 workgroups (column products in 64-column tiles), then one workgroup
+    each (the two wider ones take the 1024-column tiles): one IPM iteration
+    whose PCG runs 30 iterations, against the oracle's step driven by its
+    own Jacobi PCG for 30 iterations.  The data are float32 values, stored
+    as such on the GPU and summed in float64 on both sides."""
     from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options, default_pcg_options
     from oracle.pcg import pcg
     specs = W.batch_stratified(3, 256, 32, strata=[0, 1, 2])
     qb = QPBatch(specs, precision="fp32")
-    qb.set_teams([1, 4, 16])
+    qb.set_teams(teams)
     opts = default_ipm_options(max_iter=1, pcg=default_pcg_options(tol=1e-300, maxit=30))
     infos, st = qb.solve(opts)
     assert st == 0
