@@ -123,7 +123,7 @@ __device__ __forceinline__ bool blo(double l) { return l > -INFINITY; }
 __device__ __forceinline__ bool bhi(double u) { return u < INFINITY; }
 
 // The workgroups solving one instance together.  Work is spread over the
-// team's threads (tid, nthr), waves (wave, nwave) and 256-column tiles; the
+// team's threads (tid, nthr), waves (wave, nwave) and column tiles; the
 // team's phases are separated by team_sync.  A team of one is a workgroup:
 // its barrier is __syncthreads and its reductions stay in LDS.
 struct Team {
@@ -143,7 +143,9 @@ struct Team {
 // Team barrier: every member's writes so far are visible to every member
 // after it.  Thread 0 of each member releases its workgroup's writes at
 // device scope, counts its arrival and waits for the count of this barrier,
-// then acquires; the workgroup's own barrier brackets it.
+// then acquires; the workgroup's own barrier brackets it.  Every member
+// then reads the launch's abort flag (set by a wait that gave up) into
+// t.dead, so all of them leave at their next check.
 __device__ __noinline__ void team_sync(Team& t) {
   __shared__ int aborted;
   __syncthreads();
