@@ -40,12 +40,21 @@ def test_stored_traffic_is_keyed_to_the_sources(tmp_path, monkeypatch):
     assert bench.stored_traffic("w", "fp64", "colpass") is None      # other kernel sources
 
 
-def test_source_digest_covers_every_hip_source(tmp_path, monkeypatch):
+def test_source_digest_covers_the_single_path_sources(tmp_path, monkeypatch):
+    """The digest changes with any source of the single-instance path's
+    kernels and launches, and not with the batched solver's own file."""
     csrc = tmp_path / "paper_2308_00637_amd" / "csrc"
     csrc.mkdir(parents=True)
-    (csrc / "a.hip").write_text("x")
-    (csrc / "b.h").write_text("y")
+    for f in bench.PATH_SOURCES:
+        (csrc / f).write_text(f)
+    (csrc / "qpk_batch.hip").write_text("z")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     d0 = bench.source_digest()
-    (csrc / "b.h").write_text("y // comment")
-    assert bench.source_digest() != d0
+    (csrc / "qpk_batch.hip").write_text("z // other")
+    assert bench.source_digest() == d0
+    for f in bench.PATH_SOURCES:
+        (csrc / f).write_text(f + " // comment")
+        d1 = bench.source_digest()
+        assert d1 != d0
+        d0 = d1
+    assert set(bench.PATH_SOURCES) == {"qpk_api.hip", "qpk_internal.h", "qpk_kernels.hip"}
