@@ -47,8 +47,9 @@ def parse():
     ap.add_argument("--workload", default="rt_full",
                     choices=["rt_full", "rt_small", "svm_full", "svm_rbf", "qn_rt", "tiny_dense",
                              "batch3"])
-    ap.add_argument("--batch-take", type=int, default=32,
-                    help="batch3: instances of the 256-instance uneven batch, spread over its sizes")
+    ap.add_argument("--batch-take", type=int, default=256,
+                    help="batch3: instances of the 256-instance uneven batch, spread over its sizes "
+                         "(all 256 by default; generating them takes about two minutes)")
     ap.add_argument("--batch-cg", type=int, default=40,
                     help="batch3: PCG iterations of the first Newton system timed per instance")
     ap.add_argument("--tune-table", default="",
