@@ -105,6 +105,8 @@ struct TeamPlan {
   int32_t* abort;
   int32_t spin_max;
   int32_t nqueue;   // queues, by team size, largest first
+  double* part;     // ld float64 per workgroup of the launch: column partial sums
+  int32_t ld;
 };
 
 template <typename T>
@@ -134,6 +136,8 @@ struct Team {
   unsigned long long gen;   // barriers passed
   int slot;                 // next reduction slot
   int dead;                 // the launch was aborted: leave at once
+  double* part;             // the team's column partial sums, member q at part + q * ld
+  int ld;
   __device__ int tid() const { return r * kBB + static_cast<int>(threadIdx.x); }
   __device__ int nthr() const { return G * kBB; }
   __device__ int wave() const { return r * kBW + static_cast<int>(threadIdx.x >> 6); }
@@ -314,9 +318,8 @@ __device__ __noinline__ void rowdots(const Team& tm, const T* __restrict__ M, in
 // columns per member of the team): 1024-column tiles, one column per thread,
 // each thread walking all rows in order, so a workgroup reads 4 KB of each
 // of kUnroll consecutive rows per batch (close to a plain stream's rate).
-// Narrow ones: 64-column tiles spread over the team's workgroups (so even a
-// team of 64 finds work), sixteen row groups per tile, combined in LDS in
-// group order.
+// One workgroup on a narrow operator: 64-column tiles, sixteen row groups
+// per tile, combined in LDS in group order.
 constexpr int kTileW = 64, kTileRG = kBB / kTileW;
 template <bool SQ, typename T>
 __device__ __noinline__ void coldots_wide(const Team& tm, const T* __restrict__ M, int R, int Cn,
@@ -398,10 +401,63 @@ __device__ __noinline__ void coldots_tiles(const Team& tm, const T* __restrict__
   }
 }
 
+// A team too large for a wide tile each: every member sums its own slab of
+// rows (R / G of them, in order) over all columns in 1,024-column tiles into
+// its row of the team's partial sums; after a team barrier each member adds
+// the G partials of its share of the columns in rank order.  The barrier at
+// the end keeps the partials until every member has read them.
 template <bool SQ, typename T>
-__device__ __forceinline__ void coldots(const Team& tm, const T* __restrict__ M, int R, int Cn,
+__device__ __noinline__ void coldots_slabs(Team& tm, const T* __restrict__ M, int R, int Cn,
+                                           const double* __restrict__ w, double* __restrict__ out) {
+  gmem<double>* wg = as_global(w);
+  const int r0 = static_cast<int>(static_cast<int64_t>(R) * tm.r / tm.G);
+  const int r1 = static_cast<int>(static_cast<int64_t>(R) * (tm.r + 1) / tm.G);
+  double* mine = tm.part + static_cast<int64_t>(tm.r) * tm.ld;
+  for (int c0 = 0; c0 < Cn; c0 += kBB) {
+    const int c = c0 + static_cast<int>(threadIdx.x);
+    const int off = min(static_cast<int>(threadIdx.x), Cn - 1 - c0);  // in bounds
+    double acc = 0.0;
+    for (int r = r0; r < r1; r += kUnroll) {
+      T a[kUnroll];
+      if (r + kUnroll <= r1) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) a[u] = as_global(M + static_cast<int64_t>(r + u) * Cn + c0)[off];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double d = static_cast<double>(a[u]);
+          acc += (SQ ? d * d : d) * wg[r + u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+          a[u] = as_global(M + static_cast<int64_t>(min(r + u, r1 - 1)) * Cn + c0)[off];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const double d = r + u < r1 ? static_cast<double>(a[u]) : 0.0;
+          const double ww = r + u < r1 ? wg[r + u] : 0.0;
+          acc += (SQ ? d * d : d) * ww;
+        }
+      }
+    }
+    if (c < Cn) mine[c] = acc;
+  }
+  team_sync(tm);
+  for (int c = tm.tid(); c < Cn; c += tm.nthr()) {
+    double t = 0.0;
+    for (int q = 0; q < tm.G; ++q) t += tm.part[static_cast<int64_t>(q) * tm.ld + c];
+    out[c] = t;
+  }
+  team_sync(tm);
+}
+
+// Wide operators: 1,024-column tiles, alternate members taking alternate
+// tiles; a team larger than that sums row slabs (above); one workgroup on a
+// narrow operator: 64-column tiles.
+template <bool SQ, typename T>
+__device__ __forceinline__ void coldots(Team& tm, const T* __restrict__ M, int R, int Cn,
                                         const double* __restrict__ w, double* __restrict__ out) {
   if (Cn >= 768 * tm.G) coldots_wide<SQ>(tm, M, R, Cn, w, out);
+  else if (tm.G > 1) coldots_slabs<SQ>(tm, M, R, Cn, w, out);
   else coldots_tiles<SQ>(tm, M, R, Cn, w, out);
 }
 
@@ -785,6 +841,7 @@ __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
   __shared__ int slot;
   Team tm;
   tm.G = 1; tm.r = 0; tm.ts = nullptr; tm.abort = nullptr; tm.spin_max = 0; tm.dead = 0;
+  tm.part = nullptr; tm.ld = 0;
   int home = 0, nq = 1;
   if (a.plan.team_of) {
     const int t = a.plan.team_of[blockIdx.x];
@@ -795,6 +852,8 @@ __global__ __launch_bounds__(kBB) void k_batch_ipm(BArgs<T> a) {
     tm.spin_max = a.plan.spin_max;
     home = a.plan.queue[t];
     nq = a.plan.nqueue;
+    tm.part = a.plan.part + static_cast<int64_t>(a.plan.first[t]) * a.plan.ld;
+    tm.ld = a.plan.ld;
   }
   tm.gen = 0;
   tm.slot = 0;
@@ -912,10 +971,13 @@ struct qp_batch_s {
   int64_t plan_cap = 0;           // int32 entries of d_plan
   TeamSync* d_sync = nullptr;
   int sync_cap = 0;
+  double* d_part = nullptr;       // column partial sums of team members: part_ld per workgroup
+  int64_t part_cap = 0;           // float64 entries of d_part
+  int32_t part_ld = 1;            // the largest column count of any operator (n or k)
   int last_grid = 0, last_teams = 0;
   ~qp_batch_s() {
     for (void* p : {(void*)d_inst, (void*)d_order, (void*)d_next, d_vals, (void*)d_vec, (void*)d_out,
-                    (void*)d_plan, (void*)d_sync})
+                    (void*)d_plan, (void*)d_sync, (void*)d_part})
       if (p) (void)hipFree(p);
   }
 };
@@ -984,6 +1046,7 @@ static qp_status batch_create_impl(qp_batch b, const qp_desc* ds, int32_t count)
     a_off[i] = vals; vals += d.m * d.n;
     h_off[i] = vals; vals += I.hkind ? d.n * d.k : d.n * d.n;
     I.v_off = vecs; vecs += BLayout(I.n, I.m, I.k).total;
+    b->part_ld = std::max(b->part_ld, std::max(I.n, I.k));
   }
   // host staging, then one upload each
   std::vector<double> hv(vecs, 0.0);
@@ -1070,6 +1133,19 @@ static int32_t team_spin_limit() {
   int32_t lim = 1 << 23;
   if (const char* e = std::getenv("QPK_BATCH_SPIN")) lim = std::max(1, std::atoi(e));
   return lim;
+}
+
+// Room for `wgs` workgroups' column partial sums (grown, never shrunk).
+static qp_status ensure_part(qp_batch b, int wgs) {
+  const int64_t need = static_cast<int64_t>(wgs) * b->part_ld;
+  if (need > b->part_cap) {
+    if (b->d_part) (void)hipFree(b->d_part);
+    b->d_part = nullptr;
+    b->part_cap = 0;
+    BCHK(hipMalloc((void**)&b->d_part, sizeof(double) * need));
+    b->part_cap = need;
+  }
+  return QP_OK;
 }
 
 static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
@@ -1169,6 +1245,10 @@ static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
   plan->abort = P + o_abort;
   plan->spin_max = team_spin_limit();
   plan->nqueue = nq;
+  qp_status ps = ensure_part(b, W);
+  if (ps != QP_OK) return ps;
+  plan->part = b->d_part;
+  plan->ld = b->part_ld;
   *grid = W;
   b->last_grid = W;
   b->last_teams = teams;
@@ -1352,6 +1432,10 @@ static qp_status probe_team(qp_batch b, int id, int g, const BOpts& bo, double* 
   plan.qorder = P + o_qorder; plan.sync = b->d_sync; plan.abort = P + o_abort;
   plan.spin_max = team_spin_limit();
   plan.nqueue = 1;
+  qp_status ps = ensure_part(b, g);
+  if (ps != QP_OK) return ps;
+  plan.part = b->d_part;
+  plan.ld = b->part_ld;
   hipEvent_t e0, e1;
   BCHK(hipEventCreate(&e0));
   BCHK(hipEventCreate(&e1));

@@ -93,8 +93,12 @@ def test_batch_rejects_unsupported_inputs():
 def test_teams_of_workgroups_match_one_workgroup_per_instance_and_the_oracle():
     """Teams of 2, 4 and 8 workgroups (and teams of one beside them, each size
     with its own queue) in one cooperative launch: per instance the same
-    solve as one workgroup per instance to rounding (the teams' reductions
-    add the members' partials in rank order) and the oracle's optimum."""
+    optimum as one workgroup per instance and as the oracle.  The teams add
+    the same products in another order (reductions over the members'
+    partials in rank order, column sums over row slabs), and these Newton
+    systems often run the PCG to its 5,000-iteration cap, where an inexact
+    step's rounding can steer the IPM path: the iteration counts may differ
+    by a few (never more than 15%), the optima may not."""
     from paper_2308_00637_amd.qpk import QPBatch
     rng = np.random.default_rng(31)
     specs = []
@@ -115,7 +119,7 @@ def test_teams_of_workgroups_match_one_workgroup_per_instance_and_the_oracle():
         rel = abs(a.objective - b.objective) / max(1.0, abs(b.objective))
         print(f"  {i}: n={specs[i].n} team {sizes[i]}: ipm {a.iterations}/{b.iterations} "
               f"cg {a.total_cg_iters}/{b.total_cg_iters} obj rel {rel:.1e}", flush=True)
-        assert a.result == 0 and abs(a.iterations - b.iterations) <= 1
+        assert a.result == 0 and abs(a.iterations - b.iterations) <= max(1, 0.15 * b.iterations)
         assert rel <= 1e-9
     check(specs, team, qb)
 
@@ -144,8 +148,8 @@ def test_team_barrier_give_up_is_reported_and_the_next_launch_is_clean(monkeypat
     monkeypatch.delenv("QPK_BATCH_SPIN")
     team, st1 = qb.solve()
     assert st1 == 0
-    for a, b in zip(team, solo):
-        assert a.result == 0 and abs(a.iterations - b.iterations) <= 1
+    for a, b in zip(team, solo):   # the same optima (iteration counts as in the test above)
+        assert a.result == 0 and abs(a.iterations - b.iterations) <= max(1, 0.15 * b.iterations)
         assert abs(a.objective - b.objective) <= 1e-9 * max(1.0, abs(b.objective))
 
 
@@ -166,13 +170,12 @@ def test_autotune_picks_teams_from_measurements_and_reuses_its_table(tmp_path):
     """qp_batch_autotune times each size class's largest instance with teams
     of 1, 2, 4, ... workgroups, keeps the times in a table and gives the
     largest instances the largest teams; a second batch with the same
-    classes reads the table and measures nothing.  A bounded solve with the
-    tuned teams agrees with one workgroup per instance to what the PCG
-    tolerance allows after three IPM steps (each Newton system solved to a
-    relative residual of 1e-7, the two adding their partial sums in
-    different orders: the large instance's column products walk all rows in
-    one sum on one workgroup and sixteen row groups per tile on a team)."""
-    from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options
+    classes reads the table and measures nothing.  With the tuned teams one
+    IPM iteration whose PCG runs exactly 30 iterations agrees with one
+    workgroup per instance to rounding (the two add the same products in
+    other orders; a PCG stopped by its tolerance instead could stop one
+    iteration apart and steer the IPM path)."""
+    from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options, default_pcg_options
     rng = np.random.default_rng(41)
     specs = [W.dense_qp(rng, n, int(1.5 * n), n // 2, name=f"a{n}")
              for n in (1500, 900, 400, 150, 150, 150)]
@@ -185,15 +188,56 @@ def test_autotune_picks_teams_from_measurements_and_reuses_its_table(tmp_path):
     assert sizes[0] == max(sizes) and sizes[0] >= 4 and sizes[3] <= sizes[0]
     sizes2, probes2 = QPBatch(specs).autotune(table)
     assert probes2 == 0 and sizes2 == sizes
-    o = default_ipm_options(max_iter=3)
+    o = default_ipm_options(max_iter=1, pcg=default_pcg_options(tol=1e-300, maxit=30))
     tuned, st = qb.solve(o)
     qb.set_teams(None)
     solo, st0 = qb.solve(o)
     assert st == 0 and st0 == 0
     for a, b in zip(tuned, solo):
-        assert a.iterations == b.iterations == 3
-        assert a.rnorm == pytest.approx(b.rnorm, rel=1e-5)
-        assert a.objective == pytest.approx(b.objective, rel=1e-5)
+        assert a.iterations == b.iterations == 1 and a.total_cg_iters == b.total_cg_iters == 30
+        assert a.rnorm == pytest.approx(b.rnorm, rel=1e-8)
+        assert a.objective == pytest.approx(b.objective, rel=1e-8)
+
+
+def test_wide_column_tiles_split_over_a_team_against_oracle_pcg():
+    """Operators wide enough for 1,024-column tiles on every member of a
+    team (A of n = 1,600 on two workgroups, n = 3,100 on four: the members
+    take alternate tiles, the last one partial), and narrower ones whose
+    column sums the team splits into row slabs (A of n = 1,200 on four, and
+    every H factor of n/2 columns here): one IPM iteration with 30 PCG
+    iterations against the oracle's step driven by its own Jacobi PCG, and
+    the same instances on one workgroup each."""
+    from paper_2308_00637_amd.qpk import QPBatch, default_ipm_options, default_pcg_options
+    from oracle.pcg import pcg
+    rng = np.random.default_rng(17)
+    specs = [W.dense_qp(rng, n, m, n // 2, round_f32=True, name=f"w{n}")
+             for n, m in ((1600, 1900), (3100, 3300), (1200, 1500))]
+    opts = default_ipm_options(max_iter=1, pcg=default_pcg_options(tol=1e-300, maxit=30))
+
+    def direction(prob, st_, mu, res):
+        rhs, _ = O.newton_rhs_doubly(prob, st_, mu)
+        dg = O.jacobi_diagonal(prob, st_, mu)
+        sol, _, _, _ = pcg(lambda v: O.kkt_matvec(prob, st_, mu, v), rhs, dg, tol=1e-300, maxit=30)
+        return O.direction_from_solution(prob, st_, res, sol)
+
+    refs = [O.solve(O.from_spec(sp), O.IPMOptions(max_iter=1), direction=direction) for sp in specs]
+    for teams in ([2, 4, 4], None):
+        qb = QPBatch(specs, precision="fp32")
+        qb.set_teams(teams)
+        infos, st = qb.solve(opts)
+        assert st == 0
+        for i, sp in enumerate(specs):
+            prob = O.from_spec(sp)
+            ref = refs[i]
+            x, lam, s = qb.solution(i)
+            gst = from_masked(prob, x.cpu().numpy(), lam.cpu().numpy(), s.cpu().numpy())
+            ex = np.max(np.abs(gst.x - ref.state.x)) / max(1.0, np.max(np.abs(ref.state.x)))
+            es = np.max(np.abs(gst.s_lA - ref.state.s_lA)) / max(1.0, np.max(np.abs(ref.state.s_lA)))
+            print(f"teams {teams} n={sp.n} m={sp.m}: x {ex:.1e}, s {es:.1e}, "
+                  f"rnorm {infos[i].rnorm:.6g} / {ref.log[0]['rnorm']:.6g}", flush=True)
+            assert infos[i].total_cg_iters == 30
+            assert ex <= 1e-8 and es <= 1e-8
+            assert infos[i].rnorm == pytest.approx(ref.log[0]["rnorm"], rel=1e-8)
 
 
 @pytest.mark.parametrize("teams", [[1, 4, 16], None])
