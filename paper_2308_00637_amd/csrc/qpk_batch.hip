@@ -233,9 +233,9 @@ __device__ __forceinline__ double team_sum(Team& t, double v) {
 constexpr int kUnroll = 16;
 
 // The operators and vectors live in device memory.  Addressing them as
-// global memory from a wave-uniform base (scalar registers) plus the lane's
-// offset keeps the address arithmetic out of the vector registers and the
-// loads off the counter that LDS and scalar loads share.
+// global memory (not flat) keeps the loads off the counter that LDS and
+// scalar loads share, so a wait for either does not drain the operator
+// loads in flight; the row and tile bases are made wave-uniform.
 template <typename T>
 using gmem = const __attribute__((address_space(1))) T;
 template <typename T>
