@@ -602,10 +602,23 @@ def bench_batch(args):
         cg = sum(f.total_cg_iters for f in infos)
         byts = sum(b * f.total_cg_iters for b, f in zip(per_it, infos))
         wg, teams = qb.launch_shape()
-        print(f"[bench] {label}: {wg} workgroups, {teams} teams, {ms:.1f} ms, {cg} PCG iterations",
+        # the launch's timeline from the device clock: how much of the
+        # workgroups' time went to solving and when the last instance began
+        t0, t1, g = qb.instance_times()
+        span = max(t1)
+        busy = sum(gi * (b - a) for a, b, gi in zip(t0, t1, g))
+        longest = max(range(len(t0)), key=lambda i: t1[i] - t0[i])
+        timeline = {"span_ms": span, "last_start_ms": max(t0),
+                    "busy_fraction": busy / (wg * span) if span > 0 else None,
+                    "longest_ms": t1[longest] - t0[longest], "longest_n": ns[longest],
+                    "longest_team": g[longest]}
+        print(f"[bench] {label}: {wg} workgroups, {teams} teams, {ms:.1f} ms, {cg} PCG iterations; "
+              f"busy {timeline['busy_fraction']:.2f}, last start {timeline['last_start_ms']:.0f} ms, "
+              f"longest {timeline['longest_ms']:.0f} ms (n {ns[longest]}, team {g[longest]})",
               file=sys.stderr, flush=True)
         return {"ms": ms, "pcg_iterations": cg, "pcg_iters_per_s": cg / (ms / 1e3),
-                "GBs": byts / (ms / 1e3) / 1e9, "workgroups": wg, "teams": teams}
+                "GBs": byts / (ms / 1e3) / 1e9, "workgroups": wg, "teams": teams,
+                "timeline": timeline}
 
     run("warm-up, one workgroup per instance")
     solo = run("one workgroup per instance")

@@ -368,6 +368,12 @@ qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size);
 qp_status qp_batch_autotune(qp_batch b, const char* table_path, int32_t max_team, int32_t* team_out,
                             int32_t* probes_out);
 qp_status qp_batch_launch_shape(qp_batch b, int32_t* workgroups, int32_t* teams);
+/* Per instance of the last completed ipm_solve_batch: when its team started
+ * and finished it, in ms from the earliest start (the device's constant-rate
+ * wall clock), and the workgroups of the team that solved it (a team whose
+ * queue ran out may have taken it from another queue).  HOST arrays of
+ * `count`, each may be NULL.  QP_ERR_ARG before any completed solve. */
+qp_status qp_batch_instance_times(qp_batch b, double* start_ms, double* end_ms, int32_t* team);
 qp_status qp_batch_get_solution(qp_batch b, int32_t i, double* x, double* lam, double* s);
 const char* qp_batch_last_error(qp_batch b);
 

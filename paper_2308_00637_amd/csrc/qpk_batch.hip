@@ -72,8 +72,9 @@ struct BOpts {
 // Per-instance result (float64 fields, then counters).
 struct BResult {
   double mu_final, rnorm, primal, dual, compl_, objective;
-  int32_t status, iterations, cg_hits, pad;
+  int32_t status, iterations, cg_hits, team;   // team: workgroups that solved it
   int64_t total_cg;
+  int64_t t_start, t_end;                      // device wall clock around its solve
 };
 
 // A team's state in device memory: its barrier's arrival count (monotonic
@@ -738,6 +739,7 @@ __device__ __noinline__ void recover_ratio(Team& tm, const BInst* bi, double* ve
 
 template <typename T>
 __device__ __forceinline__ void solve_one(Team& tm, const BArgs<T>& a, int id) {
+  const int64_t t_start = wall_clock64();
   const Inst<T> I(a.inst[id], a.vec);
   const int n = I.n, m = I.m;
   const BOpts& o = a.o;
@@ -826,7 +828,8 @@ __device__ __forceinline__ void solve_one(Team& tm, const BArgs<T>& a, int id) {
     BResult r{};
     r.mu_final = mu; r.rnorm = nrm[0]; r.primal = nrm[1]; r.dual = nrm[2]; r.compl_ = nrm[3];
     r.objective = ob; r.status = status; r.iterations = it > o.max_iter ? o.max_iter : it;
-    r.cg_hits = hits; r.total_cg = total;
+    r.cg_hits = hits; r.total_cg = total; r.team = tm.G;
+    r.t_start = t_start; r.t_end = wall_clock64();
     a.out[id] = r;
   }
   team_sync(tm);
@@ -975,6 +978,7 @@ struct qp_batch_s {
   int64_t part_cap = 0;           // float64 entries of d_part
   int32_t part_ld = 1;            // the largest column count of any operator (n or k)
   int last_grid = 0, last_teams = 0;
+  bool have_out = false;          // out holds a completed launch's results
   ~qp_batch_s() {
     for (void* p : {(void*)d_inst, (void*)d_order, (void*)d_next, d_vals, (void*)d_vec, (void*)d_out,
                     (void*)d_plan, (void*)d_sync, (void*)d_part})
@@ -1334,8 +1338,10 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
   };
   BCHK(b->f32 ? go((float*)nullptr) : go((double*)nullptr));
   BCHK(hipEventRecord(e1, b->st));
+  b->have_out = false;
   BCHK(hipMemcpyAsync(b->out.data(), b->d_out, sizeof(BResult) * b->count, hipMemcpyDeviceToHost, b->st));
   BCHK(hipStreamSynchronize(b->st));
+  b->have_out = true;
   float ms = 0.f;
   BCHK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
@@ -1381,11 +1387,17 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
 // iteration taken from events around the launch.  The measurements are kept
 // in a text table (one line per measurement: device architecture, precision,
 // H kind, class, team size, microseconds per PCG iteration) that later calls
-// read instead of timing again.  Then, starting from teams of one, the
-// instance whose iteration takes longest gets twice the team while that
+// read instead of timing again.  An instance's iteration time in the batch
+// is the larger of its class's measured time (scaled by its share of the
+// representative's work) and its operator bytes over its team's share of the
+// chip's bandwidth when every workgroup streams at once (kLoadedGBs over the
+// workgroups that fit, per member): measured alone, a lone workgroup streams
+// faster than it can when all of them do.  Then, starting from teams of one,
+// the instance whose iteration takes longest gets twice the team while that
 // lowers the estimated makespan: the larger of the slowest instance's
 // iteration time and the total workgroup time over the workgroups that fit.
 constexpr int kProbeIters = 24;
+constexpr double kLoadedGBs = 5500.0;   // the batch loops' aggregate rate with every CU busy
 
 struct TuneKey {
   std::string arch;
@@ -1544,7 +1556,9 @@ qp_status qp_batch_autotune(qp_batch b, const char* table_path, int32_t max_team
     int rep = i;
     for (auto& r : reps) if (r.first == k) rep = r.second;
     const double scale = inst_work(b->inst[i]) / std::max(inst_work(b->inst[rep]), 1e-300);
-    for (auto& m : *v) if (m.first == g) return m.second * scale;
+    const double bytes = inst_work(b->inst[i]) * (b->f32 ? 4.0 : 8.0);
+    const double loaded_us = bytes / (g * kLoadedGBs / cap * 1e3);
+    for (auto& m : *v) if (m.first == g) return std::max(m.second * scale, loaded_us);
     return INFINITY;
   };
   std::vector<int32_t> team(b->count, 1);
@@ -1598,6 +1612,30 @@ qp_status qp_batch_launch_shape(qp_batch b, int32_t* workgroups, int32_t* teams)
   if (!b) return QP_ERR_ARG;
   if (workgroups) *workgroups = b->last_grid;
   if (teams) *teams = b->last_teams;
+  return QP_OK;
+}
+
+qp_status qp_batch_instance_times(qp_batch b, double* start_ms, double* end_ms, int32_t* team) {
+  if (!b) return QP_ERR_ARG;
+  if (!b->have_out) {
+    b->err = "no completed ipm_solve_batch on this batch yet";
+    return QP_ERR_ARG;
+  }
+  int dev = 0, khz = 0;
+  BCHK(hipGetDevice(&dev));
+  BCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) {
+    b->err = "the device reports no wall clock rate";
+    return QP_ERR_HIP;
+  }
+  int64_t t0 = INT64_MAX;
+  for (const BResult& r : b->out) t0 = std::min(t0, r.t_start);
+  for (int i = 0; i < b->count; ++i) {
+    const BResult& r = b->out[i];
+    if (start_ms) start_ms[i] = static_cast<double>(r.t_start - t0) / khz;
+    if (end_ms) end_ms[i] = static_cast<double>(r.t_end - t0) / khz;
+    if (team) team[i] = r.team;
+  }
   return QP_OK;
 }
 

@@ -89,7 +89,7 @@ EXPORTS = [
     "qp_update_data", "qp_fused_layout",
     "qp_batch_create", "qp_batch_destroy", "ipm_solve_batch", "qp_batch_get_solution",
     "qp_batch_last_error", "ipm_solve_dense_noalloc", "qp_batch_set_teams", "qp_batch_launch_shape",
-    "qp_batch_autotune", "qp_graph_stats",
+    "qp_batch_autotune", "qp_graph_stats", "qp_batch_instance_times",
 ]
 PROF_CATEGORIES = ("rowpass", "colpass", "tsreduce", "epilogue", "cg_update", "cg_pupdate", "fused")
 
@@ -134,6 +134,7 @@ def _load():
         "qp_batch_last_error": (C.c_char_p, [vp]),
         "qp_batch_set_teams": (C.c_int, [vp, _i32p]),
         "qp_batch_launch_shape": (C.c_int, [vp, _i32p, _i32p]),
+        "qp_batch_instance_times": (C.c_int, [vp, _dp, _dp, _i32p]),
         "qp_batch_autotune": (C.c_int, [vp, C.c_char_p, C.c_int32, _i32p, _i32p]),
         "qp_graph_stats": (C.c_int, [vp, _i64p, _i64p]),
         "ipm_solve_dense_noalloc": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp, vp, vp, vp, vp,
@@ -492,6 +493,15 @@ class QPBatch:
         w, t = C.c_int32(), C.c_int32()
         self._check_status(LIB.qp_batch_launch_shape(self.h, C.byref(w), C.byref(t)))
         return int(w.value), int(t.value)
+
+    def instance_times(self):
+        """(start_ms, end_ms, team) per instance of the last completed solve:
+        device wall-clock times from the earliest start, and the workgroups
+        of the team that solved it."""
+        k = len(self.specs)
+        t0, t1, g = (C.c_double * k)(), (C.c_double * k)(), (C.c_int32 * k)()
+        self._check_status(LIB.qp_batch_instance_times(self.h, t0, t1, g))
+        return list(t0), list(t1), [int(v) for v in g]
 
     def _check_status(self, st):
         if st != QP_OK:

@@ -115,6 +115,10 @@ def test_teams_of_workgroups_match_one_workgroup_per_instance_and_the_oracle():
           f"(one workgroup each: {solo[0].time_ms:.1f} ms)", flush=True)
     assert st0 == 0 and st1 == 0
     assert 4 <= teams <= wg <= 1024
+    t0, t1, g = qb.instance_times()
+    assert min(t0) == 0.0 and all(0.0 <= a <= b for a, b in zip(t0, t1))
+    assert max(t1) <= team[0].time_ms + 1.0
+    assert all(gi >= si for gi, si in zip(g, sizes))   # its own queue's team, or a larger one helping
     for i, (a, b) in enumerate(zip(team, solo)):
         rel = abs(a.objective - b.objective) / max(1.0, abs(b.objective))
         print(f"  {i}: n={specs[i].n} team {sizes[i]}: ipm {a.iterations}/{b.iterations} "
