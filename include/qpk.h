@@ -360,10 +360,14 @@ qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size);
  * NULL: nothing read or kept), one line per measurement: device
  * architecture, float32 storage (0/1), H kind, class, team size,
  * microseconds per PCG iteration; measurements found there are not taken
- * again.  Starting from teams of one, the instance with the longest PCG
- * iteration gets twice the team while that lowers the estimated makespan
- * (the larger of the slowest iteration and the total workgroup time over the
- * co-resident workgroups).  HOST outs, may be NULL: team_out (one per
+ * again.  An instance's iteration time is taken as the larger of its
+ * class's time (scaled by its work) and its operator bytes over its team's
+ * share of 5.5 TB/s among the co-resident workgroups (a workgroup alone
+ * streams faster than beside all the others).  Starting from teams of one,
+ * the instance with the longest PCG iteration gets twice the team while
+ * that lowers the estimated makespan (the larger of the slowest iteration
+ * and the total workgroup time over the co-resident workgroups).  HOST
+ * outs, may be NULL: team_out (one per
  * instance), probes_out (measurements taken by this call). */
 qp_status qp_batch_autotune(qp_batch b, const char* table_path, int32_t max_team, int32_t* team_out,
                             int32_t* probes_out);
