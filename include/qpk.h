@@ -342,8 +342,10 @@ qp_status ipm_solve_batch(qp_batch b, const ipm_options* o, int32_t workgroups, 
  * (so results differ from a team of one by rounding only).  With any size
  * above 1, ipm_solve_batch makes one cooperative launch of at most the
  * co-resident workgroups (and at most `workgroups` when positive): each team
- * size gets its own queue of instances and a number of teams in proportion to
- * its instances' work; a team whose queue is empty then takes instances from
+ * size gets its own queue of instances, longest first, and a number of teams
+ * in proportion to its instances' workgroup time (the autotuner's estimates
+ * when qp_batch_autotune set the sizes, else their operator work); a team
+ * whose queue is empty then takes instances from
  * the queues of smaller team sizes (which team solves an instance, and so
  * its rounding, can differ between launches).  A team whose members cannot
  * all be resident is reported as QP_ERR_HIP rather than waited for.

@@ -970,6 +970,9 @@ struct qp_batch_s {
   std::vector<BResult> out;
   // team launches: the team size of each instance (all 1: one workgroup each)
   std::vector<int32_t> team;
+  // the autotuner's estimate of each instance's PCG iteration on its team
+  // (us; empty when the sizes came from qp_batch_set_teams)
+  std::vector<double> t_est;
   int32_t* d_plan = nullptr;      // team_of | first | size | queue | qstart | qcount | qnext | qorder | abort
   int64_t plan_cap = 0;           // int32 entries of d_plan
   TeamSync* d_sync = nullptr;
@@ -1159,14 +1162,17 @@ static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
   const int nq = (int)sizes.size();
   std::vector<double> qwork(nq, 0.0);
   std::vector<std::vector<int32_t>> qinst(nq);
+  // an instance's weight: the autotuner's estimate of its iteration on its
+  // team (workgroup time = that times the team), else its operator work
+  const bool est = b->t_est.size() == static_cast<size_t>(b->count);
+  auto weight = [&](int i) { return est ? b->t_est[i] : inst_work(b->inst[i]); };
   std::vector<int32_t> order(b->count);
   for (int i = 0; i < b->count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return inst_work(b->inst[x]) > inst_work(b->inst[y]); });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return weight(x) > weight(y); });
   for (int i : order) {
     const int q = (int)(std::find(sizes.begin(), sizes.end(), b->team[i]) - sizes.begin());
     qinst[q].push_back(i);
-    qwork[q] += inst_work(b->inst[i]);
+    qwork[q] += est ? b->t_est[i] * sizes[q] : inst_work(b->inst[i]);
   }
   double tot = 0.0;
   for (double w : qwork) tot += w;
@@ -1198,6 +1204,46 @@ static qp_status build_plan(qp_batch b, int cap, TeamPlan* plan, int* grid) {
       }
     if (worst < 0) break;
     --nteams[worst];
+  }
+  if (est) {
+    // with estimates: simulate each queue (its teams taking its instances in
+    // order, each as soon as it is free) and move workgroups from the queue
+    // that finishes first to the one that finishes last while that helps
+    auto finish = [&](int q, int nt) {
+      std::vector<double> free_at(std::max(nt, 1), 0.0);
+      for (int i : qinst[q]) {
+        auto it = std::min_element(free_at.begin(), free_at.end());
+        *it += b->t_est[i];
+      }
+      return *std::max_element(free_at.begin(), free_at.end());
+    };
+    for (int step = 0; step < 4 * cap; ++step) {
+      int qmax = 0, qmin = -1;
+      std::vector<double> fin(nq);
+      for (int q = 0; q < nq; ++q) {
+        fin[q] = finish(q, nteams[q]);
+        if (fin[q] > fin[qmax]) qmax = q;
+      }
+      if (nteams[qmax] >= (int)qinst[qmax].size()) break;   // one team per instance already
+      const double gain = finish(qmax, nteams[qmax] + 1);
+      if (total_wg() + sizes[qmax] <= cap) {
+        ++nteams[qmax];
+        continue;
+      }
+      // free sizes[qmax] workgroups from the queue that would finish first
+      // without them
+      double best = INFINITY;
+      for (int q = 0; q < nq; ++q) {
+        if (q == qmax) continue;
+        const int drop = (sizes[qmax] + sizes[q] - 1) / sizes[q];
+        if (nteams[q] - drop < 1) continue;
+        const double f = finish(q, nteams[q] - drop);
+        if (f < best) { best = f; qmin = q; }
+      }
+      if (qmin < 0 || !(std::max(best, gain) < fin[qmax])) break;
+      nteams[qmin] -= (sizes[qmax] + sizes[qmin] - 1) / sizes[qmin];
+      ++nteams[qmax];
+    }
   }
   int teams = 0;
   for (int q = 0; q < nq; ++q) teams += nteams[q];
@@ -1586,6 +1632,8 @@ qp_status qp_batch_autotune(qp_batch b, const char* table_path, int32_t max_team
     cur = next;
   }
   b->team = team;
+  b->t_est.assign(b->count, 0.0);
+  for (int i = 0; i < b->count; ++i) b->t_est[i] = t_of(i, team[i]);
   if (team_out) std::copy(team.begin(), team.end(), team_out);
   if (probes_out) *probes_out = probes;
   return QP_OK;
@@ -1605,6 +1653,7 @@ qp_status qp_batch_set_teams(qp_batch b, const int32_t* team_size) {
     }
   }
   b->team = t;
+  b->t_est.clear();
   return QP_OK;
 }
 
